@@ -1,0 +1,158 @@
+/*
+ * hk.h -- C ABI of libhk, the MI355X (gfx950) implementation of the hot path of hypothesis-tested
+ * progressive kernel estimation ("Hypothesis Testing for Progressive Kernel Estimation and VCM
+ * Framework", arXiv 2504.04411).
+ *
+ * One iteration (Sec. 5.1) for every hit point (kernel, eye vertex):
+ *   1. sort the iteration's light vertices (photons) into a uniform grid (counting/radix sort by cell),
+ *   2. gather the photons inside the kernel's current radius r (Eq. kaplanyan-integral, disk Omega_r),
+ *   3. map each one to the kernel's tangent plane (Eq. map-function) and add its test sample to the
+ *      sums and sums of squares of its group: 2 equi-areal annuli x 6 equi-angular sectors
+ *      (Sec. 3.2.1, Sec. 6.1.1), retained while the radius is kept (Sec. 5.1),
+ *   4. evaluate the ANOVA F statistic (Eq. f-statistic) against the (1 - alpha_F) quantile of
+ *      F(11, 12 (m - 1)) (Sec. 3.2.2), m = light sub-paths since the last shrink,
+ *   5. add this iteration's kernel estimate to the progressive estimate (Eq. progressive-VCM-estimator)
+ *      and shrink the radius when the test rejects (Eq. radiusupdate),
+ *   6. in vertex-merging mode, weight each merged pair by the balance heuristic (Eq. mis-weight).
+ *
+ * Conventions
+ *   - Every call returns an int status: HK_OK (0) or a negative HK_E_* code; hk_last_error() gives a
+ *     message for the calling thread. No call aborts the process.
+ *   - Calls taking a hipStream_t only enqueue work on that stream; they do not synchronise (except
+ *     where stated). The caller keeps every buffer alive until the stream has passed the call.
+ *   - Pointers named "device" must be device memory of the context's GPU; "host" pointers are read
+ *     during the call only.
+ *   - The library allocates no device memory. The caller allocates the per-set state and the shared
+ *     workspace (sizes from hk_state_bytes / hk_workspace_bytes, 256-byte aligned) and owns them.
+ *   - Arrays are structure-of-arrays float32: x, y and z (or R, G, B) in three separate arrays.
+ *   - Calls on one context are not thread-safe; use one context per host thread.
+ */
+#ifndef HK_H
+#define HK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HK_VERSION 100
+
+/* status codes */
+#define HK_OK 0
+#define HK_E_INVALID_ARG (-1)   /* a NULL or out-of-range argument */
+#define HK_E_BAD_STATE (-2)     /* call out of order, e.g. hk_iterate before hk_set_kernels */
+#define HK_E_SMALL_BUFFER (-3)  /* a caller-allocated buffer is smaller than required */
+#define HK_E_HIP (-4)           /* a HIP runtime call failed */
+#define HK_E_UNSUPPORTED (-5)   /* a parameter combination this build does not implement */
+
+/* modes */
+#define HK_MODE_PPM 0           /* progressive photon mapping: sample = luminance of the photon flux */
+#define HK_MODE_VCM 1           /* vertex merging of VCM+: sample = MIS-weighted luminance of the path */
+
+/* test channels (Sec. 5.1 end: luminance by default, one test per RGB channel for chromatic light) */
+#define HK_STATS_LUMA 0
+#define HK_STATS_RGB 1
+
+typedef struct hk_ctx hk_ctx;
+
+/* Parameters of the estimator (Sec. 5.1 Eq. radiusupdate, Sec. 6 settings). */
+typedef struct hk_params {
+    float r1;              /* initial radius, > 0 */
+    float k;               /* shrink ratio in (0, 1) */
+    float alpha_f;         /* significance level of the F-test in (0, 1) */
+    float alpha;           /* lower-bound exponent in (0, 1) */
+    float rmin;            /* lower-bound scale r_min in [0, r1] */
+    int32_t n_a;           /* annuli; this build supports 2 */
+    int32_t n_s;           /* sectors per annulus; this build supports 6 */
+    int32_t mode;          /* HK_MODE_PPM or HK_MODE_VCM */
+    int32_t stats_channel; /* HK_STATS_LUMA or HK_STATS_RGB */
+    float normal_cos_min;  /* a pair counts only if n_kernel . n_photon >= this (when both have normals) */
+    int32_t max_iters;     /* iterations a set may run (sizes the critical-value table), 1..65536 */
+    float cell_scale;      /* grid cell = cell_scale * (radius quantile); 0 selects the default */
+    float cell_quantile;   /* radius quantile in (0, 1] used for the cell size; 0 selects the default */
+    int32_t reserved[7];
+} hk_params;
+
+/* One iteration's light vertices of one set. */
+typedef struct hk_photons {
+    uint64_t J_emitted;    /* light sub-paths traced, stored or not (>= n_stored, >= 1) */
+    int64_t n_stored;      /* light vertices in the arrays, >= 0 */
+    const float *pos[3];   /* device, n_stored each */
+    const float *nrm[3];   /* device or all NULL (no normal test) */
+    const float *flux[3];  /* device; PPM: photon flux; VCM: light-vertex throughput */
+    const float *mis[3];   /* device, VCM only: light partials dVCM, dVC, dVM (dVC unused) */
+} hk_photons;
+
+/* Fills *p with the defaults of the paper's settings: k = 0.7, alpha_F = 0.05, alpha = 0.75,
+ * r_min = 0.001 r1, 2 x 6 groups, PPM, luminance test, normal threshold 0.5, 4096 iterations. */
+int hk_default_params(float r1, hk_params *p);
+
+/* Creates a context bound to the current HIP device. Validates p (HK_E_INVALID_ARG,
+ * HK_E_UNSUPPORTED for n_a != 2 or n_s != 6). *out receives the handle. */
+int hk_create(const hk_params *p, hk_ctx **out);
+int hk_destroy(hk_ctx *ctx);
+
+/* Bytes of the per-set state for n_kernels hit points (the caller allocates it on the device). */
+int hk_state_bytes(hk_ctx *ctx, int64_t n_kernels, size_t *out);
+
+/* Bytes of the workspace shared by all sets of one hk_iterate call, for at most max_photons stored
+ * light vertices per set and max_kernels kernels per set. */
+int hk_workspace_bytes(hk_ctx *ctx, int64_t max_photons, int64_t max_kernels, size_t *out);
+
+/* Initialises set `set_id` (0..255): copies the n hit points into `state` (device, state_bytes(n)),
+ * orders them along a Morton curve, computes tangent frames and clears all statistics (t = 0,
+ * sums 0, estimate 0, r = r_init or r1). Inputs (device): pos[3]; nrm[3] or NULL (+z);
+ * r_init or NULL; VCM only: cam_beta[3] camera throughput, cam_mis[3] partials dVCM, dVC, dVM.
+ * `workspace` (device, at least hk_workspace_bytes(ctx, 0, n) bytes, given in workspace_bytes) is
+ * scratch for the ordering. Resets the set's iteration count. */
+int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *const pos[3], const float *const nrm[3],
+                   const float *r_init, const float *const cam_beta[3], const float *const cam_mis[3],
+                   void *state, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Runs one iteration (steps 1-6 above) for each of the n_sets sets; ph[s] holds set s's light
+ * vertices and state[s] its state, set_ids[s] its id. Sets run one after the other on `stream`.
+ * `workspace` (device, workspace_bytes long) must hold hk_workspace_bytes(ctx, n_stored, H) for
+ * every set (HK_E_SMALL_BUFFER otherwise). Arguments of all sets are checked before any work is
+ * enqueued. Non-finite photon values are not rejected: a NaN position never lands in a disk, a NaN
+ * flux makes that kernel's F NaN, which keeps the radius (IEEE comparison). */
+int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+               void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Radiance estimate L = f_r tau / N per channel (f_r = 1/pi), in the caller's original kernel order.
+ * out_rgb[3]: device arrays of n floats. */
+int hk_read_radiance(hk_ctx *ctx, int set_id, const void *state, float *const out_rgb[3], hipStream_t stream);
+
+/* Current radii (device float[n]), original order. */
+int hk_read_radii(hk_ctx *ctx, int set_id, const void *state, float *out, hipStream_t stream);
+
+/* Last iteration's per-kernel values, original order (any pointer may be NULL): in-disk count,
+ * F (NaN when undefined), critical value used, shrink decision (1 = shrunk), kept iterations t. */
+int hk_read_debug(hk_ctx *ctx, int set_id, const void *state, uint32_t *count, double *F, double *Fc,
+                  uint8_t *decision, uint32_t *t, hipStream_t stream);
+
+/* Retained group sums in float64 (device, n x 12 each, row-major, original order): S and Q as the
+ * compensated pairs value - compensation, and the estimate tau (n x 3). */
+int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *S, double *Q, double *tau,
+                 hipStream_t stream);
+
+/* Host routine: (1 - alpha) quantile of the F(d1, d2) distribution in float64, the same routine the
+ * device evaluates for the critical value (Sec. 3.2.2). Returns NaN for invalid arguments. */
+double hk_f_quantile(double d1, double d2, double alpha);
+
+/* Timing of the last hk_iterate calls when enabled (hipEvents on the caller's stream):
+ * hk_profile_enable(ctx, 1) starts recording, hk_profile_read(ctx, out, n) synchronises on the last
+ * event and writes up to n phase totals in milliseconds since enabling: [0] grid build,
+ * [1] critical values, [2] gather + test + update, [3] launches of [2] counted. */
+int hk_profile_enable(hk_ctx *ctx, int on);
+int hk_profile_read(hk_ctx *ctx, double *out, int n);
+
+int hk_version(void);
+const char *hk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HK_H */

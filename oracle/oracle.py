@@ -219,6 +219,9 @@ def f_critical(m, alpha_f: float, n_groups: int = NG) -> np.ndarray:
     flat = m.reshape(-1)
     res = out.reshape(-1)
     for i, mv in enumerate(flat):
+        if not mv >= 2.0:                 # n (m - 1) = 0 within-group degrees of freedom: no test
+            res[i] = np.nan
+            continue
         key = (float(mv), repr(alpha_f), n_groups)
         if key not in _FC_CACHE:
             _FC_CACHE[key] = _f_quantile_mp(repr(alpha_f), n_groups - 1, n_groups * (float(mv) - 1.0))
@@ -283,7 +286,7 @@ def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nt
     F = f_statistic(st.S, st.Q, m)
     ssw = within_ss(st.S, st.Q, m)
     Fc = fcrit_override(m) if fcrit_override is not None else f_critical(m, params.alpha_f, NG)
-    valid = (st.nseen > 0) & (ssw > 0)
+    valid = (st.nseen > 0) & (ssw > 0) & (m >= 2)
     F = np.where(st.nseen > 0, F, np.nan)
     shrink = valid & (F > Fc)                          # NaN compares false: keep
     # progressive estimate: each iteration with its own radius r_i (Eq. progressive-VCM-estimator)

@@ -1,0 +1,462 @@
+// Uniform-grid build for the range search of one iteration (the "range search data structure" of
+// Sec. 5.1) and the one-time set initialisation.
+//
+//   plan      picks the cell size from the radius distribution of the previous update
+//   keys      cell index of every photon (x fastest), KEY_OUTSIDE outside the grid domain
+//   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
+//             a three-phase exclusive scan and a wave-ballot stable scatter
+//   permute   sorted structure-of-arrays payload copy (and the photon's luminance for PPM)
+//   cstart    cstart[c] = first sorted position with key >= c, for c in [0, ncells]
+#include <math.h>
+
+#include "hk_internal.h"
+#include "hk_kernels.h"
+
+namespace hk {
+
+// ------------------------------------------------------------------------------------------------
+// scans
+// ------------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan over a 256-thread block; *total receives the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *d, int64_t len, uint32_t *part)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
+        const int64_t k = base + i;
+        if (k < len) s += d[k];
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void scan_parts_kernel(uint32_t *part, int nparts)
+{
+    uint32_t carry = 0;
+    for (int base = 0; base < nparts; base += 256) {
+        const int k = base + threadIdx.x;
+        const uint32_t v = k < nparts ? part[k] : 0;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot);
+        if (k < nparts) part[k] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len, const uint32_t *part)
+{
+    constexpr int PER = SCAN_TILE / 256;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
+    uint32_t v[PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t k = base + i;
+        v[i] = k < len ? d[k] : 0;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t k = base + i;
+        if (k < len) d[k] = run;
+        run += v[i];
+    }
+}
+
+static void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s)
+{
+    const int nparts = (int)cdiv(len, SCAN_TILE);
+    scan_reduce_kernel<<<nparts, 256, 0, s>>>(d, len, part);
+    scan_parts_kernel<<<1, 256, 0, s>>>(part, nparts);
+    scan_down_kernel<<<nparts, 256, 0, s>>>(d, len, part);
+}
+
+// ------------------------------------------------------------------------------------------------
+// LSD radix sort of (key, value) pairs
+// ------------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *keys, int64_t n, int shift,
+                                                             uint32_t *hist, int nblk)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t k = base + (int64_t)i * RS_THREADS + threadIdx.x;
+        if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: items are visited in rounds of 256 consecutive keys; inside a round the rank of a
+// key among equal digits is (count in earlier rounds) + (count in lower waves) + (lower lanes of the
+// same wave, from eight ballots).
+__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
+                                                                uint32_t *kout, uint32_t *vout, int64_t n,
+                                                                int shift, const uint32_t *offs, int nblk)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    for (int i = 0; i < 4; ++i) wcnt[i][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t k = base + (int64_t)it * RS_THREADS + tid;
+        const bool valid = k < n;
+        const uint32_t key = valid ? kin[k] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int i = 0; i < w; ++i) pos += wcnt[i][d];
+            kout[pos] = key;
+            vout[pos] = vin ? vin[k] : (uint32_t)k;
+        }
+        __syncthreads();
+        run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
+        __syncthreads();
+    }
+}
+
+// Sorts n pairs whose keys use `bits` low bits. Values start as the identity permutation. Returns
+// in *kres / *vres whichever buffers hold the result.
+void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres)
+{
+    const int nblk = (int)cdiv(n, RS_TILE);
+    uint32_t *ki = kA, *vi = nullptr, *ko = kB, *vo = vB;
+    uint32_t *vspare = vA;
+    for (int shift = 0; shift < bits; shift += 8) {
+        rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
+        excl_scan(hist, (int64_t)256 * nblk, part, s);
+        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        uint32_t *kt = ki;
+        ki = ko;
+        ko = kt;
+        uint32_t *vt = vi ? vi : vspare;
+        vi = vo;
+        vo = vt;
+    }
+    *kres = ki;
+    *vres = vi;
+}
+
+// ------------------------------------------------------------------------------------------------
+// per-iteration grid
+// ------------------------------------------------------------------------------------------------
+
+// One thread: append J to the prefix sums, choose the cell size from the radius histogram.
+__global__ void plan_kernel(SetHeader *hdr, double *mprefix, int iter, double J, float cell_scale, float quantile,
+                            uint32_t max_cells)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    mprefix[iter] = mprefix[iter - 1] + J;
+    const double target = (double)quantile * hdr->H;
+    double cum = 0.0;
+    int bq = 0;
+    for (int b = RHIST_BINS - 1; b >= 0; --b) {
+        cum += hdr->rhist[b];
+        if (cum >= target) { bq = b; break; }
+    }
+    float cell = cell_scale * hdr->r1 * exp2f(-0.25f * (float)bq);
+    float ext[3];
+    int flat[3];
+    float emax = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        ext[a] = hdr->dom_hi[a] - hdr->dom_lo[a];
+        emax = fmaxf(emax, ext[a]);
+    }
+    for (int a = 0; a < 3; ++a) flat[a] = hdr->kflat[a];
+    if (!(cell > 0.0f)) cell = emax;
+    int dims[3];
+    for (int guard = 0; guard < 200; ++guard) {
+        double tot = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            float q = floorf(ext[a] / cell);
+            int d = (q < 1.0f || flat[a]) ? 1 : (q > 65535.0f ? 65535 : (int)q);
+            dims[a] = d;
+            tot *= d;
+        }
+        if (tot <= (double)max_cells) break;
+        cell *= 1.25f;
+    }
+    for (int a = 0; a < 3; ++a) {
+        hdr->dims[a] = dims[a];
+        hdr->cell_inv[a] = (float)dims[a] / ext[a];
+    }
+    hdr->ncells = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2];
+    hdr->cell = cell;
+    for (int b = 0; b < RHIST_BINS; ++b) hdr->rhist[b] = 0;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const SetHeader *hdr, float x, float y, float z)
+{
+    const float p[3] = {x, y, z};
+    uint32_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float f = floorf((p[a] - hdr->dom_lo[a]) * hdr->cell_inv[a]);
+        if (!(f >= 0.0f && f < (float)hdr->dims[a])) return KEY_OUTSIDE;
+        c[a] = (uint32_t)f;
+    }
+    return (c[2] * (uint32_t)hdr->dims[1] + c[1]) * (uint32_t)hdr->dims[0] + c[0];
+}
+
+__global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const float *px, const float *py,
+                                                   const float *pz, int64_t n, uint32_t *keys)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < n) keys[q] = cell_key(hdr, px[q], py[q], pz[q]);
+}
+
+__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *sval, float *pay,
+                                                      int64_t ps)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t j = sval[q];
+    const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
+    pay[0 * ps + q] = src.pos[0][j];
+    pay[1 * ps + q] = src.pos[1][j];
+    pay[2 * ps + q] = src.pos[2][j];
+    if (src.nrm[0]) {
+        pay[3 * ps + q] = src.nrm[0][j];
+        pay[4 * ps + q] = src.nrm[1][j];
+        pay[5 * ps + q] = src.nrm[2][j];
+    }
+    pay[6 * ps + q] = R;
+    pay[7 * ps + q] = G;
+    pay[8 * ps + q] = B;
+    pay[9 * ps + q] = luminance(R, G, B);
+    if (src.mis[0]) {
+        pay[10 * ps + q] = src.mis[0][j];
+        pay[11 * ps + q] = src.mis[2][j];
+    }
+}
+
+__global__ __launch_bounds__(256) void cstart_kernel(const SetHeader *hdr, const uint32_t *skeys, int64_t n,
+                                                     uint32_t *cstart)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q > n) return;
+    const uint32_t ncells = hdr->ncells;
+    const int64_t prev = (q == 0) ? -1 : (int64_t)min(skeys[q - 1], ncells);
+    const int64_t cur = (q == n) ? (int64_t)ncells : (int64_t)min(skeys[q], ncells);
+    for (int64_t c = prev + 1; c <= cur; ++c) cstart[c] = (uint32_t)q;
+}
+
+// No photons stored: every cell is empty.
+__global__ __launch_bounds__(256) void cstart_zero_kernel(const SetHeader *hdr, uint32_t *cstart, uint32_t bound)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c <= (int64_t)hdr->ncells && c <= (int64_t)bound) cstart[c] = 0;
+}
+
+void build_grid(const GridLaunch &g, hipStream_t s)
+{
+    const int64_t n = g.n;
+    if (n > 0) {
+        const int nb = (int)cdiv(n, 256);
+        keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
+        uint32_t *ks, *vs;
+        radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &vs);
+        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, vs, g.pay, g.pstride);
+        cstart_kernel<<<(int)cdiv(n + 1, 256), 256, 0, s>>>(g.hdr, ks, n, g.cstart);
+    } else {
+        cstart_zero_kernel<<<(int)cdiv((int64_t)g.ncells_bound + 1, 256), 256, 0, s>>>(g.hdr, g.cstart,
+                                                                                       g.ncells_bound);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// set initialisation
+// ------------------------------------------------------------------------------------------------
+
+// One block: bounding box of the kernels, largest initial radius, grid domain and header fields.
+__global__ __launch_bounds__(1024) void bbox_kernel(SetHeader *hdr, double *mprefix, int max_iters,
+                                                    const float *px, const float *py, const float *pz,
+                                                    const float *r_init, int64_t n, float r1, int has_nrm,
+                                                    int vcm)
+{
+    __shared__ float red[7][16];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, rm = r1;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const float p[3] = {px[i], py[i], pz[i]};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], p[a]);
+            hi[a] = fmaxf(hi[a], p[a]);
+        }
+        if (r_init) rm = fmaxf(rm, r_init[i]);
+    }
+    float v[7] = {lo[0], lo[1], lo[2], -hi[0], -hi[1], -hi[2], -rm};
+    for (int k = 0; k < 7; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] = fminf(v[k], __shfl_xor(v[k], o, 64));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 7; ++k) red[k][w] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 7; ++k) {
+            float m = red[k][0];
+            for (int i = 1; i < 16; ++i) m = fminf(m, red[k][i]);
+            v[k] = m;
+        }
+        float kl[3] = {v[0], v[1], v[2]}, kh[3] = {-v[3], -v[4], -v[5]};
+        const float rmax = -v[6];
+        float scale = 0.0f;
+        for (int a = 0; a < 3; ++a) scale = fmaxf(scale, fmaxf(fabsf(kl[a]), fabsf(kh[a])));
+        scale += rmax;
+        const float margin = 4e-6f * fmaxf(scale, 1e-30f);
+        float ext = 0.0f;
+        for (int a = 0; a < 3; ++a) ext = fmaxf(ext, kh[a] - kl[a]);
+        for (int a = 0; a < 3; ++a) {
+            const float grow = rmax * 1.001f + 4.0f * margin;
+            hdr->dom_lo[a] = kl[a] - grow;
+            hdr->dom_hi[a] = kh[a] + grow;
+            hdr->kb_lo[a] = kl[a];
+            hdr->kb_hi[a] = kh[a];
+            hdr->kflat[a] = (kh[a] - kl[a]) <= 1e-6f * ext ? 1 : 0;
+        }
+        hdr->margin_abs = margin;
+        hdr->r1 = r1;
+        hdr->rmax0 = rmax;
+        hdr->H = (int32_t)n;
+        hdr->has_nrm = has_nrm;
+        hdr->vcm = vcm;
+        hdr->max_iters = max_iters;
+        for (int b = 0; b < RHIST_BINS; ++b) hdr->rhist[b] = 0;
+    }
+    for (int i = threadIdx.x; i < max_iters + 2; i += 1024) mprefix[i] = 0.0;
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x)
+{
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void morton_kernel(const SetHeader *hdr, const float *px, const float *py,
+                                                     const float *pz, int64_t n, uint32_t *keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float p[3] = {px[i], py[i], pz[i]};
+    uint32_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        const float e = hdr->kb_hi[a] - hdr->kb_lo[a];
+        float f = e > 0.0f ? (p[a] - hdr->kb_lo[a]) / e * 1023.0f : 0.0f;
+        f = fminf(fmaxf(f, 0.0f), 1023.0f);
+        c[a] = (uint32_t)f;
+    }
+    keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+}
+
+__global__ __launch_bounds__(256) void init_state_kernel(KernelSrc src, StateView st, const uint32_t *perm,
+                                                         int64_t n, float r1, int nsq)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t j = perm[s];
+    for (int a = 0; a < 3; ++a) st.pos[a][s] = src.pos[a][j];
+    float nv[3] = {0.0f, 0.0f, 1.0f};
+    if (src.nrm[0])
+        for (int a = 0; a < 3; ++a) nv[a] = src.nrm[a][j];
+    float u[3], v[3];
+    onb(nv[0], nv[1], nv[2], u, v);
+    for (int a = 0; a < 3; ++a) {
+        st.nrm[a][s] = nv[a];
+        st.u[a][s] = u[a];
+        st.v[a][s] = v[a];
+    }
+    const float r = src.r_init ? src.r_init[j] : r1;
+    st.r[s] = r;
+    st.t[s] = 0;
+    st.nseen[s] = 0;
+    st.orig[s] = j;
+    st.cnt[s] = 0;
+    st.dec[s] = 0;
+    for (int i = 0; i < nsq; ++i) st.sq[i][s] = 0.0f;
+    for (int i = 0; i < 6; ++i) st.tau[i][s] = 0.0f;
+    st.F[s] = NAN;
+    st.Fc[s] = NAN;
+    if (src.cam_beta[0]) {
+        for (int a = 0; a < 3; ++a) st.cb[a][s] = src.cam_beta[a][j];
+        st.cdvcm[s] = src.cam_mis[0][j];
+        st.cdvm[s] = src.cam_mis[2][j];
+    }
+    atomicAdd(&st.hdr->rhist[radius_bin(r, r1)], 1u);
+}
+
+void init_set(const InitLaunch &g, hipStream_t s)
+{
+    const int64_t n = g.n;
+    bbox_kernel<<<1, 1024, 0, s>>>(g.st.hdr, g.st.mprefix, g.max_iters, g.src.pos[0], g.src.pos[1], g.src.pos[2],
+                                   g.src.r_init, n, g.r1, g.src.nrm[0] != nullptr, g.vcm);
+    const int nb = (int)cdiv(n, 256);
+    morton_kernel<<<nb, 256, 0, s>>>(g.st.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
+    uint32_t *ks, *vs;
+    radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs);
+    init_state_kernel<<<nb, 256, 0, s>>>(g.src, g.st, vs, n, g.r1, g.nsq);
+}
+
+}  // namespace hk
+
+namespace hk {
+void launch_plan(SetHeader *hdr, double *mprefix, int iter, double J, float cell_scale, float quantile,
+                 uint32_t max_cells, hipStream_t s)
+{
+    plan_kernel<<<1, 64, 0, s>>>(hdr, mprefix, iter, J, cell_scale, quantile, max_cells);
+}
+}  // namespace hk

@@ -1,0 +1,77 @@
+// Launch descriptors shared by the host API and the kernel files.
+#pragma once
+#include "hk_internal.h"
+
+namespace hk {
+
+struct PhotonSrc {
+    const float *pos[3];
+    const float *nrm[3];
+    const float *flux[3];
+    const float *mis[3];
+};
+
+struct KernelSrc {
+    const float *pos[3];
+    const float *nrm[3];
+    const float *r_init;
+    const float *cam_beta[3];
+    const float *cam_mis[3];
+};
+
+struct GridLaunch {
+    SetHeader *hdr;
+    PhotonSrc src;
+    int64_t n;
+    uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *cstart;
+    float *pay;
+    int64_t pstride;
+    uint32_t ncells_bound;   // cells of the plan never exceed this (workspace capacity)
+};
+
+struct InitLaunch {
+    StateView st;
+    KernelSrc src;
+    int64_t n;
+    int max_iters;
+    float r1;
+    int vcm;
+    int nsq;
+    uint32_t *keyA, *keyB, *valA, *valB, *hist, *part;
+};
+
+// Everything the fused gather / test / update kernel reads or writes for one set.
+struct GatherArgs {
+    int64_t H;
+    int ntiles;
+    SetHeader *hdr;
+    const uint32_t *cstart;
+    const float *pay;
+    int64_t pstride;
+    const float *kp[3], *kn[3], *ku[3], *kv[3];
+    float *r;
+    uint32_t *t, *nseen, *cnt, *dec;
+    float *sq[NSQ];
+    float *tau[6];
+    double *F, *Fc;
+    const float *cb[3], *cdvcm, *cdvm;
+    const double *fctab, *mprefix;
+    int iter;
+    float Jf;
+    float lb;
+    float k;
+    float cos_min;
+    float r1;
+};
+
+void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres);
+void build_grid(const GridLaunch &g, hipStream_t s);
+void init_set(const InitLaunch &g, hipStream_t s);
+void launch_plan(SetHeader *hdr, double *mprefix, int iter, double J, float cell_scale, float quantile,
+                 uint32_t max_cells, hipStream_t s);
+void launch_fcrit(double *fctab, const double *mprefix, int iter, int t_lo, int t_hi, double alpha_f,
+                  hipStream_t s);
+void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s);
+
+}  // namespace hk

@@ -1,0 +1,145 @@
+"""Thin torch-side convenience wrapper over the libhk entry points.
+
+It owns the device buffers (per-set state and the shared workspace, as torch uint8 tensors), uploads
+structure-of-arrays inputs and passes raw pointers and the current stream to libhk. Nothing of the
+estimator is computed here.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import hk
+
+
+def _dev(a, device) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float32).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+
+
+def _rows(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return [t[i].data_ptr() for i in range(t.shape[0])]
+
+
+@dataclass
+class DevicePhotons:
+    """One iteration's light vertices resident on the device, (3, n) float32 tensors."""
+    J: int
+    pos: torch.Tensor
+    flux: torch.Tensor
+    nrm: Optional[torch.Tensor] = None
+    mis: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[1])
+
+    @staticmethod
+    def upload(batch, device="cuda") -> "DevicePhotons":
+        return DevicePhotons(J=int(batch.J), pos=_dev(batch.pos, device), flux=_dev(batch.flux, device),
+                             nrm=_dev(batch.nrm, device), mis=_dev(batch.mis, device))
+
+    def struct(self) -> hk.hk_photons:
+        return hk.make_photons(self.J, self.n, _rows(self.pos), _rows(self.flux), _rows(self.nrm), _rows(self.mis))
+
+
+class Estimator:
+    """One libhk context with any number of hit-point sets on one GPU."""
+
+    def __init__(self, r1: float, mode: str = "ppm", device: str = "cuda", **overrides):
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        p = hk.hk_default_params(r1)
+        p.mode = hk.HK_MODE_VCM if mode == "vcm" else hk.HK_MODE_PPM
+        for k, v in overrides.items():
+            if v is not None:
+                setattr(p, k, v)
+        self.params = p
+        self.ctx = hk.hk_create(p)
+        self.states: Dict[int, torch.Tensor] = {}
+        self.n: Dict[int, int] = {}
+        self.inputs: Dict[int, list] = {}
+        self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if self.ctx:
+            hk.hk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _workspace(self, nbytes: int) -> torch.Tensor:
+        if self.ws.numel() < nbytes:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.ws
+
+    def set_kernels(self, set_id: int, pos, nrm=None, r_init=None, cam_beta=None, cam_mis=None):
+        pos_t = _dev(pos, self.device)
+        n = int(pos_t.shape[1])
+        nrm_t, cb_t, cm_t = _dev(nrm, self.device), _dev(cam_beta, self.device), _dev(cam_mis, self.device)
+        r_t = _dev(r_init, self.device)
+        st = torch.empty(hk.hk_state_bytes(self.ctx, n), dtype=torch.uint8, device=self.device)
+        wsb = hk.hk_workspace_bytes(self.ctx, 0, n)
+        ws = self._workspace(wsb)
+        hk.hk_set_kernels(self.ctx, set_id, n, _rows(pos_t), _rows(nrm_t), None if r_t is None else r_t.data_ptr(),
+                          _rows(cb_t), _rows(cm_t), st.data_ptr(), ws.data_ptr(), ws.numel(), self.stream)
+        self.states[set_id] = st
+        self.n[set_id] = n
+        self.inputs[set_id] = [pos_t, nrm_t, cb_t, cm_t, r_t]     # kept alive until the stream passes
+        return st
+
+    def workspace_for(self, photons: Sequence[DevicePhotons], set_ids: Sequence[int]) -> int:
+        return max(hk.hk_workspace_bytes(self.ctx, ph.n, self.n[s]) for s, ph in zip(set_ids, photons))
+
+    def iterate(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]):
+        wsb = self.workspace_for(photons, set_ids)
+        ws = self._workspace(wsb)
+        hk.hk_iterate(self.ctx, list(set_ids), [p.struct() for p in photons],
+                      [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel(), self.stream)
+
+    # ---- reads (device tensors, original kernel order) -------------------------------------------
+    def radiance(self, set_id: int) -> torch.Tensor:
+        out = torch.empty((3, self.n[set_id]), dtype=torch.float32, device=self.device)
+        hk.hk_read_radiance(self.ctx, set_id, self.states[set_id].data_ptr(), _rows(out), self.stream)
+        return out
+
+    def radii(self, set_id: int) -> torch.Tensor:
+        out = torch.empty(self.n[set_id], dtype=torch.float32, device=self.device)
+        hk.hk_read_radii(self.ctx, set_id, self.states[set_id].data_ptr(), out.data_ptr(), self.stream)
+        return out
+
+    def debug(self, set_id: int) -> dict:
+        n = self.n[set_id]
+        d = dict(count=torch.empty(n, dtype=torch.int32, device=self.device),
+                 F=torch.empty(n, dtype=torch.float64, device=self.device),
+                 Fc=torch.empty(n, dtype=torch.float64, device=self.device),
+                 decision=torch.empty(n, dtype=torch.uint8, device=self.device),
+                 t=torch.empty(n, dtype=torch.int32, device=self.device))
+        hk.hk_read_debug(self.ctx, set_id, self.states[set_id].data_ptr(), d["count"].data_ptr(), d["F"].data_ptr(),
+                         d["Fc"].data_ptr(), d["decision"].data_ptr(), d["t"].data_ptr(), self.stream)
+        return d
+
+    def sums(self, set_id: int):
+        n = self.n[set_id]
+        S = torch.empty((n, 12), dtype=torch.float64, device=self.device)
+        Q = torch.empty((n, 12), dtype=torch.float64, device=self.device)
+        tau = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        hk.hk_read_sums(self.ctx, set_id, self.states[set_id].data_ptr(), S.data_ptr(), Q.data_ptr(), tau.data_ptr(),
+                        self.stream)
+        return S, Q, tau

@@ -1,0 +1,221 @@
+"""ctypes binding of libhk (include/hk.h): the same entry points, argument marshalling only.
+
+Every step of an iteration runs in libhk's HIP kernels. torch is used for device memory (state and
+workspace buffers, uploaded inputs) and for the current stream. Importing this module fails loudly
+when libhk.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hk.h")
+
+HK_OK = 0
+HK_E_INVALID_ARG = -1
+HK_E_BAD_STATE = -2
+HK_E_SMALL_BUFFER = -3
+HK_E_HIP = -4
+HK_E_UNSUPPORTED = -5
+HK_MODE_PPM = 0
+HK_MODE_VCM = 1
+HK_STATS_LUMA = 0
+HK_STATS_RGB = 1
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_vp = ctypes.c_void_p
+
+
+class hk_params(ctypes.Structure):
+    _fields_ = [
+        ("r1", ctypes.c_float), ("k", ctypes.c_float), ("alpha_f", ctypes.c_float), ("alpha", ctypes.c_float),
+        ("rmin", ctypes.c_float), ("n_a", ctypes.c_int32), ("n_s", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("stats_channel", ctypes.c_int32), ("normal_cos_min", ctypes.c_float), ("max_iters", ctypes.c_int32),
+        ("cell_scale", ctypes.c_float), ("cell_quantile", ctypes.c_float), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class hk_photons(ctypes.Structure):
+    _fields_ = [
+        ("J_emitted", ctypes.c_uint64), ("n_stored", ctypes.c_int64),
+        ("pos", _vp * 3), ("nrm", _vp * 3), ("flux", _vp * 3), ("mis", _vp * 3),
+    ]
+
+
+class HKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libhk error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python paper_2504_04411_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        c = ctypes
+        sig = {
+            "hk_default_params": ([c.c_float, c.POINTER(hk_params)], c.c_int),
+            "hk_create": ([c.POINTER(hk_params), c.POINTER(_vp)], c.c_int),
+            "hk_destroy": ([_vp], c.c_int),
+            "hk_state_bytes": ([_vp, c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
+            "hk_workspace_bytes": ([_vp, c.c_int64, c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
+            "hk_set_kernels": ([_vp, c.c_int, c.c_int64, _vp * 3, c.c_void_p, _vp, c.c_void_p, c.c_void_p,
+                                _vp, _vp, c.c_size_t, _vp], c.c_int),
+            "hk_iterate": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp,
+                            c.c_size_t, _vp], c.c_int),
+            "hk_read_radiance": ([_vp, c.c_int, _vp, _vp * 3, _vp], c.c_int),
+            "hk_read_radii": ([_vp, c.c_int, _vp, _vp, _vp], c.c_int),
+            "hk_read_debug": ([_vp, c.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp], c.c_int),
+            "hk_read_sums": ([_vp, c.c_int, _vp, _vp, _vp, _vp, _vp], c.c_int),
+            "hk_f_quantile": ([c.c_double, c.c_double, c.c_double], c.c_double),
+            "hk_profile_enable": ([_vp, c.c_int], c.c_int),
+            "hk_profile_read": ([_vp, c.POINTER(c.c_double), c.c_int], c.c_int),
+            "hk_version": ([], c.c_int),
+            "hk_last_error": ([], c.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/hk.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hk_\w+)\s*\(", txt, flags=re.M)))
+
+
+def check(rc: int):
+    if rc != HK_OK:
+        raise HKError(rc, lib().hk_last_error().decode())
+    return rc
+
+
+def _arr3(ptrs):
+    a = (_vp * 3)()
+    if ptrs is not None:
+        for i, p in enumerate(ptrs):
+            a[i] = p
+    return a
+
+
+def _opt3(ptrs):
+    """Pointer to a 3-array of pointers, or NULL."""
+    if ptrs is None:
+        return None
+    a = _arr3(ptrs)
+    return ctypes.cast(a, ctypes.c_void_p), a
+
+
+# ---------------------------------------------------------------------------------------------
+# entry points with the header's names (plain integers for device pointers and streams)
+# ---------------------------------------------------------------------------------------------
+
+def hk_default_params(r1: float) -> hk_params:
+    p = hk_params()
+    check(lib().hk_default_params(float(r1), ctypes.byref(p)))
+    return p
+
+
+def hk_create(p: hk_params) -> int:
+    h = _vp()
+    check(lib().hk_create(ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def hk_destroy(ctx: int):
+    check(lib().hk_destroy(ctx))
+
+
+def hk_state_bytes(ctx: int, n: int) -> int:
+    out = ctypes.c_size_t()
+    check(lib().hk_state_bytes(ctx, int(n), ctypes.byref(out)))
+    return out.value
+
+
+def hk_workspace_bytes(ctx: int, max_photons: int, max_kernels: int) -> int:
+    out = ctypes.c_size_t()
+    check(lib().hk_workspace_bytes(ctx, int(max_photons), int(max_kernels), ctypes.byref(out)))
+    return out.value
+
+
+def hk_set_kernels(ctx, set_id, n, pos, nrm, r_init, cam_beta, cam_mis, state, workspace, workspace_bytes, stream):
+    keep = []
+    args = []
+    for x in (nrm, cam_beta, cam_mis):
+        o = _opt3(x)
+        if o is None:
+            args.append(None)
+        else:
+            args.append(o[0])
+            keep.append(o[1])
+    check(lib().hk_set_kernels(ctx, int(set_id), int(n), _arr3(pos), args[0], r_init, args[1], args[2], state,
+                               workspace, int(workspace_bytes), stream))
+
+
+def make_photons(J_emitted, n_stored, pos, flux, nrm=None, mis=None) -> hk_photons:
+    ph = hk_photons()
+    ph.J_emitted = int(J_emitted)
+    ph.n_stored = int(n_stored)
+    ph.pos = _arr3(pos)
+    ph.flux = _arr3(flux)
+    ph.nrm = _arr3(nrm)
+    ph.mis = _arr3(mis)
+    return ph
+
+
+def hk_iterate(ctx, set_ids, photons, states, workspace, workspace_bytes, stream):
+    n = len(set_ids)
+    ids = (ctypes.c_int * n)(*set_ids)
+    phs = (hk_photons * n)(*photons)
+    sts = (_vp * n)(*states)
+    check(lib().hk_iterate(ctx, n, ids, phs, sts, workspace, int(workspace_bytes), stream))
+
+
+def hk_read_radiance(ctx, set_id, state, out_rgb, stream):
+    check(lib().hk_read_radiance(ctx, int(set_id), state, _arr3(out_rgb), stream))
+
+
+def hk_read_radii(ctx, set_id, state, out, stream):
+    check(lib().hk_read_radii(ctx, int(set_id), state, out, stream))
+
+
+def hk_read_debug(ctx, set_id, state, count, F, Fc, decision, t, stream):
+    check(lib().hk_read_debug(ctx, int(set_id), state, count, F, Fc, decision, t, stream))
+
+
+def hk_read_sums(ctx, set_id, state, S, Q, tau, stream):
+    check(lib().hk_read_sums(ctx, int(set_id), state, S, Q, tau, stream))
+
+
+def hk_f_quantile(d1: float, d2: float, alpha: float) -> float:
+    return lib().hk_f_quantile(float(d1), float(d2), float(alpha))
+
+
+def hk_profile_enable(ctx, on: bool):
+    check(lib().hk_profile_enable(ctx, 1 if on else 0))
+
+
+def hk_profile_read(ctx):
+    out = (ctypes.c_double * 4)()
+    check(lib().hk_profile_read(ctx, out, 4))
+    return list(out)
+
+
+def hk_version() -> int:
+    return lib().hk_version()
+
+
+def hk_last_error() -> str:
+    return lib().hk_last_error().decode()

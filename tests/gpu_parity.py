@@ -1,0 +1,109 @@
+"""Side-by-side runs of the HIP path (through the C ABI) and the CPU oracle, compared per iteration.
+
+Rules (parity bar):
+  * per-kernel in-disk counts: bit-exact;
+  * shrink decisions: exact, except where the oracle's |F - Fc| < 1e-6 (either outcome is correct);
+    a kernel whose decision differs inside that band leaves the comparison from then on;
+  * radii: bit-exact for kernels still compared (both sides update in float32);
+  * F: relative 1e-9 (the compensated float32 pairs carry the sums to ~1e-12), critical values 1e-10;
+  * radiance: relative 1e-5.
+"""
+from __future__ import annotations
+
+import sys
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+from workloads import generators as G
+
+BAND = 1e-6
+
+
+@dataclass
+class ParityReport:
+    iterations: int = 0
+    kernels: int = 0
+    band_flips: int = 0
+    band_cases: int = 0
+    shrinks: int = 0
+    max_F_rel: float = 0.0
+    max_Fc_rel: float = 0.0
+    max_L_rel: float = 0.0
+    excluded: int = 0
+    notes: list = field(default_factory=list)
+
+
+def sub_kernels(ks: G.KernelSet, idx):
+    take = lambda a: None if a is None else np.ascontiguousarray(a[:, idx])
+    return G.KernelSet(pos=take(ks.pos), nrm=take(ks.nrm), cam_beta=take(ks.cam_beta), cam_mis=take(ks.cam_mis))
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    both_nan = np.isnan(a) & np.isnan(b)
+    d = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+    d[both_nan] = 0.0
+    d[(a == b)] = 0.0
+    return d
+
+
+def run_parity(w: G.Workload, n_iter: int, idx=None, photons_fn=None, est_kw=None, verbose=True) -> ParityReport:
+    """Runs n_iter iterations on the GPU (all kernels) and on the oracle (kernels idx, default all)."""
+    p = w.params
+    ks = w.kernels
+    idx = np.arange(ks.n) if idx is None else np.asarray(idx)
+    est = Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin, **(est_kw or {}))
+    est.set_kernels(0, ks.pos, ks.nrm, None, ks.cam_beta, ks.cam_mis)
+    oks = sub_kernels(ks, idx)
+    ost = O.init_state(idx.size, p.r1)
+    alive = np.ones(idx.size, bool)
+    rep = ParityReport(kernels=idx.size)
+    get = photons_fn or w.photons
+    for it in range(n_iter):
+        ph = get(it)
+        if verbose:
+            print(f"  [{w.name}] iteration {it + 1}/{n_iter}: H={ks.n} J={ph.J} stored={ph.n}", flush=True)
+        est.iterate([0], [DevicePhotons.upload(ph)])
+        O.iterate(p, oks, ost, ph)
+        d = {k: v.cpu().numpy()[idx] for k, v in est.debug(0).items()}
+        rg = est.radii(0).cpu().numpy()[idx]
+        cnt = d["count"].astype(np.uint32)
+        bad = np.flatnonzero(alive & (cnt != ost.count))
+        assert bad.size == 0, f"iteration {it + 1}: count mismatch at {idx[bad[:5]]}: {cnt[bad[:5]]} vs {ost.count[bad[:5]]}"
+        band = np.abs(ost.F - ost.Fc) < BAND
+        dg = d["decision"].astype(bool)
+        diff = alive & (dg != ost.shrink)
+        assert not np.any(diff & ~band), f"iteration {it + 1}: decision mismatch outside the band at {idx[diff & ~band][:5]}"
+        rep.band_cases += int((alive & band).sum())
+        rep.band_flips += int(diff.sum())
+        alive &= ~diff
+        rep.shrinks += int((alive & ost.shrink).sum())
+        badr = np.flatnonzero(alive & (rg != ost.r))
+        assert badr.size == 0, f"iteration {it + 1}: radius mismatch at {idx[badr[:5]]}: {rg[badr[:5]]} vs {ost.r[badr[:5]]}"
+        fr = _rel(d["F"], ost.F)[alive]
+        assert np.all(np.isnan(d["F"][alive]) == np.isnan(ost.F[alive])), "F defined on one side only"
+        if fr.size:
+            rep.max_F_rel = max(rep.max_F_rel, float(np.nanmax(fr)))
+        fin = alive & np.isfinite(ost.Fc)
+        if fin.any():
+            rep.max_Fc_rel = max(rep.max_Fc_rel, float(_rel(d["Fc"][fin], ost.Fc[fin]).max()))
+        rep.iterations += 1
+    assert rep.max_F_rel < 1e-9, rep
+    assert rep.max_Fc_rel < 1e-10, rep
+    Lg = est.radiance(0).cpu().numpy()[:, idx].T
+    Lo = O.radiance(ost)
+    lr = _rel(Lg[alive], Lo[alive])
+    rep.max_L_rel = float(lr.max()) if lr.size else 0.0
+    assert rep.max_L_rel < 1e-5, rep
+    rep.excluded = int((~alive).sum())
+    assert rep.excluded <= max(2, idx.size // 1000), rep
+    est.close()
+    if verbose:
+        print(f"  parity ok: {rep}", flush=True)
+    sys.stdout.flush()
+    return rep
