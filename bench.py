@@ -1,0 +1,158 @@
+"""Throughput of the hypothesis-tested progressive kernel estimator on one MI355X.
+
+A step is one full iteration of the hot path (grid build, gather, grouped sums, F-test, radius and
+estimate update) over one batch of light vertices. Default workload: the box scene, 512 x 512 hit
+points on five faces of the unit box with per-point normals, 2M light sub-paths per iteration from a
+point light with a spherical occluder, 64 iterations (the whole job is timed; warm-up iterations run
+on a separate state first). Inputs are generated on the host, uploaded, and resident in HBM before
+the timed region starts.
+
+Prints one JSON line: value = queries/s (one query = one hit point in one iteration), with the
+roofline of the dominant kernel (fused gather / test / update) and the CPU oracle timed on a bounded
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Dominant-kernel work model per launch (VALU lane operations), from the hot-path measurement model:
+# 150 per kernel (load state, F in float64, update), 35 per in-disk pair (map, group, compensated
+# sums), 8 per candidate with 2.9 candidates per in-disk pair (uniform grid with cell = r).
+OPS_PER_QUERY = 150.0
+OPS_PER_PAIR = 35.0 + 8.0 * 2.9
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane per clock
+# (packed-FP32 and FMA doubling excluded; this build disables packed FP32).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def _gen(args):
+    seed, it, J = args
+    from workloads import generators as G
+    w = G.config1(seed=seed, J=J)
+    b = w.photons(it)
+    return it, b
+
+
+def make_batches(seed, n, J, workers):
+    out = [None] * n
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for it, b in ex.map(_gen, [(seed, i, J) for i in range(n)]):
+            out[it] = b
+    return out
+
+
+def cpu_baseline(w, batches, stride, nthreads):
+    """The oracle as it stands (grid mode, OpenMP over kernels) on every `stride`-th kernel for all
+    iterations; returns queries/s of that sample."""
+    from oracle import oracle as O
+    idx = np.arange(0, w.kernels.n, stride)
+    ks = w.kernels.subset(idx)
+    st = O.init_state(idx.size, w.params.r1)
+    O.f_critical(np.array([b.J * (i + 1) for i, b in enumerate(batches)], float), w.params.alpha_f)  # warm cache
+    t0 = time.perf_counter()
+    for b in batches:
+        O.iterate(w.params, ks, st, b, use_grid=True, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return idx.size * len(batches) / dt, dt, idx.size
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--photons", type=int, default=2_000_000)
+    ap.add_argument("--res", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described but "
+              "not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_04411_amd import hk
+    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+    from workloads import generators as G
+
+    hk.lib()
+    torch.cuda.set_device(0)
+    w = G.config1(seed=args.seed, res=args.res, J=args.photons)
+    K, W = args.steps, args.warmup
+    t0 = time.perf_counter()
+    batches = make_batches(args.seed, max(K, W), args.photons, args.workers)
+    print(f"# generated {len(batches)} batches in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = [DevicePhotons.upload(b) for b in batches]
+    torch.cuda.synchronize()
+
+    p = w.params
+    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)
+    for i in range(W):
+        est.iterate([0], [dev[i]])
+    torch.cuda.synchronize()
+    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)         # fresh state for the timed job
+    est._workspace(max(est.workspace_for([d], [0]) for d in dev))
+    torch.cuda.synchronize()
+    est.profile(True)
+    t0 = time.perf_counter()
+    for i in range(K):
+        est.iterate([0], [dev[i]])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = est.profile_read()
+    stats = est.stats(0)
+    radii = est.radii(0).cpu().numpy()
+    H = w.kernels.n
+    value = H * K / dt
+    gather_s = prof["gather_ms"] / 1e3
+    launch_ms = prof["gather_ms"] / max(prof["launches"], 1)
+    ops = OPS_PER_QUERY * H * K + OPS_PER_PAIR * stats["pairs"]
+    achieved = ops / gather_s / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": "gather_update_kernel<true,false>", "avg_launch_ms": round(launch_ms, 4),
+            "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
+    out = {
+        "metric": "photon-kernel queries/sec (gather+F-test+update) at 1 GPU",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(dt / K * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"box scene, {args.res}x{args.res} hit points with normals, {args.photons} photons "
+                               f"per iteration, point light and sphere occluder, {K} iterations",
+                   "H": H, "J": args.photons, "iterations": K, "seed": args.seed},
+        "gather_test_update_queries_per_s": round(H * K / gather_s, 1),
+        "phase_ms_total": {"grid": round(prof["grid_ms"], 3), "fcrit": round(prof["fcrit_ms"], 3),
+                           "gather_test_update": round(prof["gather_ms"], 3)},
+        "pairs_per_query": round(stats["pairs"] / (H * K), 2),
+        "candidates_per_pair": round(stats["candidates"] / max(stats["pairs"], 1), 3),
+        "final_radius": {"mean": float(radii.mean()), "min": float(radii.min()),
+                         "shrunk_frac": float((radii < np.float32(p.r1)).mean())},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        q, secs, nk = cpu_baseline(w, batches[:K], args.cpu_stride, nthreads)
+        out["cpu_baseline"] = {"value": round(q, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
+                               "sample": f"oracle grid mode on every {args.cpu_stride}th hit point ({nk} kernels) "
+                                         f"for all {K} iterations of the same inputs, {secs:.1f}s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

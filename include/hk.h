@@ -60,11 +60,12 @@ typedef struct hk_ctx hk_ctx;
 
 /* Parameters of the estimator (Sec. 5.1 Eq. radiusupdate, Sec. 6 settings). */
 typedef struct hk_params {
-    float r1;              /* initial radius, > 0 */
-    float k;               /* shrink ratio in (0, 1) */
-    float alpha_f;         /* significance level of the F-test in (0, 1) */
-    float alpha;           /* lower-bound exponent in (0, 1) */
-    float rmin;            /* lower-bound scale r_min in [0, r1] */
+    float r1;              /* initial radius, > 0 (radii are float32 quantities) */
+    float k;               /* shrink ratio in (0, 1), applied as a float32 multiply */
+    double alpha_f;        /* significance level of the F-test in (0, 1) */
+    double alpha;          /* lower-bound exponent in (0, 1) */
+    double rmin;           /* lower-bound scale r_min in [0, r1]; the bound is evaluated in float64 and
+                              rounded once to float32 */
     int32_t n_a;           /* annuli; this build supports 2 */
     int32_t n_s;           /* sectors per annulus; this build supports 6 */
     int32_t mode;          /* HK_MODE_PPM or HK_MODE_VCM */
@@ -73,7 +74,7 @@ typedef struct hk_params {
     int32_t max_iters;     /* iterations a set may run (sizes the critical-value table), 1..65536 */
     float cell_scale;      /* grid cell = cell_scale * (radius quantile); 0 selects the default */
     float cell_quantile;   /* radius quantile in (0, 1] used for the cell size; 0 selects the default */
-    int32_t reserved[7];
+    int32_t reserved[8];
 } hk_params;
 
 /* One iteration's light vertices of one set. */
@@ -88,7 +89,7 @@ typedef struct hk_photons {
 
 /* Fills *p with the defaults of the paper's settings: k = 0.7, alpha_F = 0.05, alpha = 0.75,
  * r_min = 0.001 r1, 2 x 6 groups, PPM, luminance test, normal threshold 0.5, 4096 iterations. */
-int hk_default_params(float r1, hk_params *p);
+int hk_default_params(double r1, hk_params *p);
 
 /* Creates a context bound to the current HIP device. Validates p (HK_E_INVALID_ARG,
  * HK_E_UNSUPPORTED for n_a != 2 or n_s != 6). *out receives the handle. */
@@ -137,6 +138,11 @@ int hk_read_debug(hk_ctx *ctx, int set_id, const void *state, uint32_t *count, d
  * compensated pairs value - compensation, and the estimate tau (n x 3). */
 int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *S, double *Q, double *tau,
                  hipStream_t stream);
+
+/* Running totals of the set since hk_set_kernels, written to out (device, 4 x uint64): [0] gather
+ * launches, [1] in-disk (kernel, photon) pairs, [2] kernel x photon candidate tests, [3] grid cells
+ * of the last iteration. */
+int hk_read_stats(hk_ctx *ctx, int set_id, const void *state, uint64_t *out, hipStream_t stream);
 
 /* Host routine: (1 - alpha) quantile of the F(d1, d2) distribution in float64, the same routine the
  * device evaluates for the critical value (Sec. 3.2.2). Returns NaN for invalid arguments. */

@@ -69,15 +69,15 @@ extern "C" int hk_version(void) { return HK_VERSION; }
 
 extern "C" const char *hk_last_error(void) { return g_err.c_str(); }
 
-extern "C" int hk_default_params(float r1, hk_params *p)
+extern "C" int hk_default_params(double r1, hk_params *p)
 {
     if (!p) return fail(HK_E_INVALID_ARG, "hk_default_params: p is NULL");
     memset(p, 0, sizeof *p);
-    p->r1 = r1;
+    p->r1 = (float)r1;
     p->k = 0.7f;
-    p->alpha_f = 0.05f;
-    p->alpha = 0.75f;
-    p->rmin = 0.001f * r1;
+    p->alpha_f = 0.05;
+    p->alpha = 0.75;
+    p->rmin = 0.001 * r1;
     p->n_a = 2;
     p->n_s = 6;
     p->mode = HK_MODE_PPM;
@@ -95,9 +95,10 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
     *out = nullptr;
     if (!finite_pos(p->r1)) return fail(HK_E_INVALID_ARG, "r1 must be finite and > 0");
     if (!(p->k > 0.0f && p->k < 1.0f)) return fail(HK_E_INVALID_ARG, "k must be in (0, 1)");
-    if (!(p->alpha_f > 0.0f && p->alpha_f < 1.0f)) return fail(HK_E_INVALID_ARG, "alpha_f must be in (0, 1)");
-    if (!(p->alpha > 0.0f && p->alpha < 1.0f)) return fail(HK_E_INVALID_ARG, "alpha must be in (0, 1)");
-    if (!(p->rmin >= 0.0f && p->rmin <= p->r1)) return fail(HK_E_INVALID_ARG, "rmin must be in [0, r1]");
+    if (!(p->alpha_f > 0.0 && p->alpha_f < 1.0)) return fail(HK_E_INVALID_ARG, "alpha_f must be in (0, 1)");
+    if (!(p->alpha > 0.0 && p->alpha < 1.0)) return fail(HK_E_INVALID_ARG, "alpha must be in (0, 1)");
+    if (!(p->rmin >= 0.0 && p->rmin <= (double)p->r1 * (1.0 + 1e-7)))
+        return fail(HK_E_INVALID_ARG, "rmin must be in [0, r1]");
     if (p->n_a != 2 || p->n_s != 6) return fail(HK_E_UNSUPPORTED, "only n_a = 2, n_s = 6 is implemented");
     if (p->mode != HK_MODE_PPM && p->mode != HK_MODE_VCM) return fail(HK_E_INVALID_ARG, "unknown mode");
     if (p->stats_channel != HK_STATS_LUMA) return fail(HK_E_UNSUPPORTED, "only the luminance test is implemented");
@@ -290,7 +291,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
 
         // critical values for t = 1..i; with a constant J only the new entry t = i changes
         const int t_lo = (S.J_const && S.fc_valid_upto == i - 1) ? i : 1;
-        launch_fcrit(st.fctab, st.mprefix, i, t_lo, i, (double)p.alpha_f, stream);
+        launch_fcrit(st.fctab, st.mprefix, i, t_lo, i, p.alpha_f, stream);
         S.fc_valid_upto = S.J_const ? i : 0;
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
 
@@ -323,7 +324,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         a.mprefix = st.mprefix;
         a.iter = i;
         a.Jf = (float)P.J_emitted;
-        a.lb = (float)((double)p.rmin * sqrt(pow((double)(i + 1), (double)p.alpha - 1.0)));
+        a.lb = (float)(p.rmin * sqrt(pow((double)(i + 1), p.alpha - 1.0)));
         a.k = p.k;
         a.cos_min = p.normal_cos_min;
         a.r1 = p.r1;
@@ -444,6 +445,31 @@ extern "C" int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *
     HIP_TRY(hipSetDevice(ctx->device));
     const StateView st = make_view(const_cast<void *>(state), layout_of(ctx, S.H));
     read_sums_kernel<<<(int)cdiv(S.H, 256), 256, 0, stream>>>(st, S.H, S_out, Q_out, tau_out);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+namespace {
+__global__ void read_stats_kernel(const SetHeader *hdr, uint64_t *out)
+{
+    if (threadIdx.x == 0) {
+        out[0] = hdr->n_launch;
+        out[1] = hdr->n_pairs;
+        out[2] = hdr->n_cand;
+        out[3] = (uint64_t)hdr->ncells;
+    }
+}
+}  // namespace
+
+extern "C" int hk_read_stats(hk_ctx *ctx, int set_id, const void *state, uint64_t *out, hipStream_t stream)
+{
+    int rc = check_read(ctx, set_id, state);
+    if (rc) return rc;
+    if (!out) return fail(HK_E_INVALID_ARG, "out is NULL");
+    const SetInfo &S = ctx->sets[set_id];
+    HIP_TRY(hipSetDevice(ctx->device));
+    const StateView st = make_view(const_cast<void *>(state), layout_of(ctx, S.H));
+    read_stats_kernel<<<1, 64, 0, stream>>>(st.hdr, out);
     HIP_TRY(hipGetLastError());
     return HK_OK;
 }

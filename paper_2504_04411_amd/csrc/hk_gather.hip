@@ -113,6 +113,7 @@ __global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
 
     float fR = 0.0f, cR = 0.0f, fG = 0.0f, cG = 0.0f, fB = 0.0f, cB = 0.0f;
     uint32_t cnt = 0;
+    unsigned long long visited = 0;      // photons staged for this tile (wave-uniform)
 
     // union of the tile's disks, grown by a rounding margin, as a box of grid cells
     const float mg = active ? fmaf(r, 1e-4f, hdr->margin_abs) : 0.0f;
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
             }
             __syncthreads();
             const int nv = (int)min((uint32_t)CHUNK, total - v0);
+            visited += (unsigned long long)nv;
             for (int k = 0; k < nv; ++k) {
                 const float4 a = chA[k];
                 const float dx = x - a.x, dy = y - a.y, dz = z - a.z;
@@ -275,6 +277,16 @@ __global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
     }
     __syncthreads();
     if (lhist[lane]) atomicAdd(&hdr->rhist[lane], lhist[lane]);
+    // tile totals for throughput accounting: in-disk pairs and lane x photon tests
+    unsigned long long pairs = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    const unsigned long long nact = (unsigned long long)__popcll(__ballot(active));
+    if (lane == 0) {
+        atomicAdd(&hdr->n_pairs, pairs);
+        atomicAdd(&hdr->n_cand, visited * nact);
+        if (blockIdx.x == 0) atomicAdd(&hdr->n_launch, 1ull);
+    }
 }
 
 void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)

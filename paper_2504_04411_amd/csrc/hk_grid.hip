@@ -373,6 +373,9 @@ __global__ __launch_bounds__(1024) void bbox_kernel(SetHeader *hdr, double *mpre
         hdr->vcm = vcm;
         hdr->max_iters = max_iters;
         for (int b = 0; b < RHIST_BINS; ++b) hdr->rhist[b] = 0;
+        hdr->n_launch = 0;
+        hdr->n_pairs = 0;
+        hdr->n_cand = 0;
     }
     for (int i = threadIdx.x; i < max_iters + 2; i += 1024) mprefix[i] = 0.0;
 }

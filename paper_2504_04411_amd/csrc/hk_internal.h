@@ -39,6 +39,10 @@ struct SetHeader {
     uint32_t ncells;
     float cell;
     int32_t pad[4];
+    // running totals since hk_set_kernels (gather launches, in-disk pairs, lane x photon tests)
+    unsigned long long n_launch;
+    unsigned long long n_pairs;
+    unsigned long long n_cand;
 };
 
 // Offsets (bytes) of every array of a set's state; each array is 256-byte aligned.

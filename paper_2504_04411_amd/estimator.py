@@ -55,7 +55,10 @@ class Estimator:
     """One libhk context with any number of hit-point sets on one GPU."""
 
     def __init__(self, r1: float, mode: str = "ppm", device: str = "cuda", **overrides):
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         torch.cuda.set_device(self.device)
         p = hk.hk_default_params(r1)
         p.mode = hk.HK_MODE_VCM if mode == "vcm" else hk.HK_MODE_PPM
@@ -143,3 +146,16 @@ class Estimator:
         hk.hk_read_sums(self.ctx, set_id, self.states[set_id].data_ptr(), S.data_ptr(), Q.data_ptr(), tau.data_ptr(),
                         self.stream)
         return S, Q, tau
+
+    def stats(self, set_id: int) -> dict:
+        out = torch.zeros(4, dtype=torch.int64, device=self.device)
+        hk.hk_read_stats(self.ctx, set_id, self.states[set_id].data_ptr(), out.data_ptr(), self.stream)
+        v = out.cpu().tolist()
+        return dict(launches=v[0], pairs=v[1], candidates=v[2], cells=v[3])
+
+    def profile(self, on: bool = True):
+        hk.hk_profile_enable(self.ctx, on)
+
+    def profile_read(self) -> dict:
+        v = hk.hk_profile_read(self.ctx)
+        return dict(grid_ms=v[0], fcrit_ms=v[1], gather_ms=v[2], launches=int(v[3]))

@@ -31,10 +31,10 @@ _vp = ctypes.c_void_p
 
 class hk_params(ctypes.Structure):
     _fields_ = [
-        ("r1", ctypes.c_float), ("k", ctypes.c_float), ("alpha_f", ctypes.c_float), ("alpha", ctypes.c_float),
-        ("rmin", ctypes.c_float), ("n_a", ctypes.c_int32), ("n_s", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("r1", ctypes.c_float), ("k", ctypes.c_float), ("alpha_f", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("rmin", ctypes.c_double), ("n_a", ctypes.c_int32), ("n_s", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("stats_channel", ctypes.c_int32), ("normal_cos_min", ctypes.c_float), ("max_iters", ctypes.c_int32),
-        ("cell_scale", ctypes.c_float), ("cell_quantile", ctypes.c_float), ("reserved", ctypes.c_int32 * 7),
+        ("cell_scale", ctypes.c_float), ("cell_quantile", ctypes.c_float), ("reserved", ctypes.c_int32 * 8),
     ]
 
 
@@ -62,7 +62,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         c = ctypes
         sig = {
-            "hk_default_params": ([c.c_float, c.POINTER(hk_params)], c.c_int),
+            "hk_default_params": ([c.c_double, c.POINTER(hk_params)], c.c_int),
             "hk_create": ([c.POINTER(hk_params), c.POINTER(_vp)], c.c_int),
             "hk_destroy": ([_vp], c.c_int),
             "hk_state_bytes": ([_vp, c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
@@ -75,6 +75,7 @@ def lib():
             "hk_read_radii": ([_vp, c.c_int, _vp, _vp, _vp], c.c_int),
             "hk_read_debug": ([_vp, c.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp], c.c_int),
             "hk_read_sums": ([_vp, c.c_int, _vp, _vp, _vp, _vp, _vp], c.c_int),
+            "hk_read_stats": ([_vp, c.c_int, _vp, _vp, _vp], c.c_int),
             "hk_f_quantile": ([c.c_double, c.c_double, c.c_double], c.c_double),
             "hk_profile_enable": ([_vp, c.c_int], c.c_int),
             "hk_profile_read": ([_vp, c.POINTER(c.c_double), c.c_int], c.c_int),
@@ -197,6 +198,10 @@ def hk_read_debug(ctx, set_id, state, count, F, Fc, decision, t, stream):
 
 def hk_read_sums(ctx, set_id, state, S, Q, tau, stream):
     check(lib().hk_read_sums(ctx, int(set_id), state, S, Q, tau, stream))
+
+
+def hk_read_stats(ctx, set_id, state, out, stream):
+    check(lib().hk_read_stats(ctx, int(set_id), state, out, stream))
 
 
 def hk_f_quantile(d1: float, d2: float, alpha: float) -> float:

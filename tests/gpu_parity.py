@@ -5,7 +5,9 @@ Rules (parity bar):
   * shrink decisions: exact, except where the oracle's |F - Fc| < 1e-6 (either outcome is correct);
     a kernel whose decision differs inside that band leaves the comparison from then on;
   * radii: bit-exact for kernels still compared (both sides update in float32);
-  * F: relative 1e-9 (the compensated float32 pairs carry the sums to ~1e-12), critical values 1e-10;
+  * F: relative 2e-7. The compensated float32 pairs carry every sum to ~1e-12, but each squared
+    sample psi^2 is rounded to float32 before it is added (relative error <= 2^-24 per term), so
+    the within-group sum, and F with it, may differ by about 6e-8 relative; critical values 1e-10;
   * radiance: relative 1e-5.
 """
 from __future__ import annotations
@@ -38,8 +40,7 @@ class ParityReport:
 
 
 def sub_kernels(ks: G.KernelSet, idx):
-    take = lambda a: None if a is None else np.ascontiguousarray(a[:, idx])
-    return G.KernelSet(pos=take(ks.pos), nrm=take(ks.nrm), cam_beta=take(ks.cam_beta), cam_mis=take(ks.cam_mis))
+    return ks.subset(idx)
 
 
 def _rel(a, b):
@@ -93,7 +94,7 @@ def run_parity(w: G.Workload, n_iter: int, idx=None, photons_fn=None, est_kw=Non
         if fin.any():
             rep.max_Fc_rel = max(rep.max_Fc_rel, float(_rel(d["Fc"][fin], ost.Fc[fin]).max()))
         rep.iterations += 1
-    assert rep.max_F_rel < 1e-9, rep
+    assert rep.max_F_rel < 2e-7, rep
     assert rep.max_Fc_rel < 1e-10, rep
     Lg = est.radiance(0).cpu().numpy()[:, idx].T
     Lo = O.radiance(ost)

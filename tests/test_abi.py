@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported(L):
 def test_default_params_and_validation(L):
     p = hk.hk_default_params(0.05)
     assert abs(p.k - 0.7) < 1e-7 and abs(p.alpha_f - 0.05) < 1e-9 and abs(p.alpha - 0.75) < 1e-7
-    assert abs(p.rmin - 5e-5) < 1e-10 and p.n_a == 2 and p.n_s == 6
+    assert p.rmin == 0.001 * 0.05 and p.n_a == 2 and p.n_s == 6
     bad = [("k", 1.0), ("k", 0.0), ("alpha_f", 1.0), ("alpha", 0.0), ("r1", -1.0), ("r1", float("nan")),
            ("rmin", 1.0), ("max_iters", 0), ("normal_cos_min", 2.0)]
     for field, val in bad:

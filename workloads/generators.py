@@ -48,6 +48,11 @@ class KernelSet:
     def n(self) -> int:
         return int(self.pos.shape[1])
 
+    def subset(self, idx) -> "KernelSet":
+        take = lambda a: None if a is None else np.ascontiguousarray(a[:, idx])
+        return KernelSet(pos=take(self.pos), nrm=take(self.nrm), cam_beta=take(self.cam_beta),
+                         cam_mis=take(self.cam_mis))
+
 
 @dataclass
 class PhotonBatch:
