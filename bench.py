@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the timed job, copy a MIB-sized device buffer once (reference for HBM "
+                         "traffic counters: it reads and writes exactly MIB MiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described but "
@@ -109,6 +112,14 @@ def main():
     est.set_kernels(0, w.kernels.pos, w.kernels.nrm)         # fresh state for the timed job
     est._workspace(max(est.workspace_for([d], [0]) for d in dev))
     torch.cuda.synchronize()
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     est.profile(True)
     t0 = time.perf_counter()
     for i in range(K):

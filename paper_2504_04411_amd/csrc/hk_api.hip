@@ -86,6 +86,7 @@ extern "C" int hk_default_params(double r1, hk_params *p)
     p->max_iters = 4096;
     p->cell_scale = 1.0f;
     p->cell_quantile = 0.5f;
+    p->heavy_cost = 4096;
     return HK_OK;
 }
 
@@ -112,6 +113,7 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
     c->p = *p;
     if (c->p.cell_scale == 0.0f) c->p.cell_scale = 1.0f;
     if (c->p.cell_quantile == 0.0f) c->p.cell_quantile = 0.5f;
+    if (c->p.heavy_cost <= 0) c->p.heavy_cost = 4096;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(HK_E_HIP, "hipGetDevice failed");
@@ -283,7 +285,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
         g.part = reinterpret_cast<uint32_t *>(w + W.part);
         g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
-        g.pay = reinterpret_cast<float *>(w + W.pay);
+        g.pay = reinterpret_cast<float4 *>(w + W.pay);
         g.pstride = P.n_stored;
         g.ncells_bound = W.max_cells;
         build_grid(g, stream);
@@ -295,13 +297,31 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         S.fc_valid_upto = S.J_const ? i : 0;
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
 
+        ListLaunch wl{};
+        wl.H = S.H;
+        wl.hdr = st.hdr;
+        wl.cstart = g.cstart;
+        for (int k = 0; k < 3; ++k) wl.kp[k] = st.pos[k];
+        wl.r = st.r;
+        wl.heavy_cost = (uint32_t)p.heavy_cost;
+        wl.flag = reinterpret_cast<uint32_t *>(w + W.flag);
+        wl.offs = reinterpret_cast<uint32_t *>(w + W.offs);
+        wl.part2 = reinterpret_cast<uint32_t *>(w + W.part2);
+        wl.heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
+        wl.light = reinterpret_cast<uint32_t *>(w + W.light);
+        wl.counts = reinterpret_cast<uint32_t *>(w + W.counts);
+        build_work_list(wl, stream);
+
         GatherArgs a{};
         a.H = S.H;
-        a.ntiles = (int)cdiv(S.H, TILE);
         a.hdr = st.hdr;
         a.cstart = g.cstart;
-        a.pay = g.pay;
-        a.pstride = g.pstride;
+        a.payA = g.pay;
+        a.payB = g.pay + g.pstride;
+        a.payC = g.pay + 2 * g.pstride;
+        a.heavy = wl.heavy;
+        a.light = wl.light;
+        a.counts = wl.counts;
         for (int k = 0; k < 3; ++k) {
             a.kp[k] = st.pos[k];
             a.kn[k] = st.nrm[k];

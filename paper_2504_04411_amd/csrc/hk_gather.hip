@@ -1,16 +1,20 @@
 // Fused gather, grouped compensated sums, ANOVA F-test and radius / estimate update for one set.
 //
-// Work decomposition: one wavefront (64 lanes) per tile of 64 kernels that are consecutive along
-// the Morton curve; lane i owns kernel i of the tile for the whole iteration, so every sum is
-// private to a lane and needs no atomics and no cross-lane reduction. The tile's photons are the
-// grid cells overlapping the union of its disks: rows of cells (x fastest) are contiguous ranges of
-// the sorted payload; the wave concatenates up to 64 rows, stages 64 photons at a time in LDS with
-// coalesced loads, and every lane tests every staged photon against its own disk (LDS broadcast).
+// Work decomposition: G lanes of a wavefront serve one kernel (hit point). The kernel's grid
+// stencil (cells overlapping the box [x - r, x + r], grown by a rounding margin) is a list of rows
+// of cells; with x fastest each row is a contiguous range of the sorted photon payload. The G lanes
+// walk the concatenated rows G photons at a time (coalesced 16-byte loads), test their photon
+// against the disk and accumulate into lane-private compensated sums kept in LDS. At the end the
+// G partial results are combined in a fixed order (deterministic) and the kernel's epilogue runs.
 //
-// Per kernel and pair inside the disk (Sec. 3.2, Sec. 5.1):
+// Light kernels use G = 16 (four kernels per wave); kernels whose stencil holds more than
+// `heavy_cost` photons get a wave of their own (G = 64) and are listed first, so the longest work
+// starts first. The list is rebuilt every iteration from the grid (cost = photons in the stencil).
+//
+// Per pair inside the disk (Sec. 3.2, Sec. 5.1):
 //   y = (<x - x*, u>, <x - x*, v>)             (Eq. map-function)
 //   g = annulus (2 d2 >= r2) x sector (60 degree wedges from +u)
-//   S_g += psi, Q_g += psi^2                  (compensated float32 pairs kept in LDS per lane)
+//   S_g += psi, Q_g += psi^2                  (compensated float32 pairs)
 //   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1)
 // Epilogue per kernel: retained sums (Sec. 5.1), F in float64 (Eq. f-statistic) against the
 // tabulated critical value for m = sum of J over the kept iterations, estimate update
@@ -23,77 +27,86 @@
 
 namespace hk {
 
-// Tile handled by workgroup b: workgroups are dealt to the 8 XCDs round-robin, so give each XCD a
-// contiguous run of tiles (spatially close kernels share photons in that XCD's L2).
-__device__ __forceinline__ int xcd_tile(int b, int n)
+__device__ __forceinline__ int wave_max_i(int v)
 {
-    const int q = n >> 3, rem = n & 7;
-    const int x = b & 7, j = b >> 3;
-    return x * q + min(x, rem) + j;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, int j)
 {
-    const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
+    for (int o = 1; o < G; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, G);
+        if (j >= o) v += u;
     }
     return v;
 }
 
-__device__ __forceinline__ float wave_min(float v)
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
     return v;
 }
 
-__device__ __forceinline__ float wave_max(float v)
+template <int G>
+__device__ __forceinline__ uint32_t group_sum_u(uint32_t v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
     return v;
 }
 
-template <bool NRM, bool VCM>
-__global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
+// Grid cells overlapping [p - r - margin, p + r + margin] on every axis; false if none.
+__device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], float r, int c0[3], int c1[3])
 {
-    __shared__ float4 slot[NG][TILE];          // per group and lane: S, comp S, Q, comp Q
-    __shared__ float4 chA[CHUNK];              // photon x, y, z, luminance
-    __shared__ float4 chN[NRM ? CHUNK : 1];    // photon normal
-    __shared__ float4 chF[CHUNK];              // flux or throughput R, G, B; dVCM
-    __shared__ float chM[VCM ? CHUNK : 1];     // dVM
-    __shared__ uint32_t rstart[64];
-    __shared__ uint32_t roff[64];
-    __shared__ uint32_t lhist[RHIST_BINS];
+    const float mg = fmaf(r, 1e-4f, hdr->margin_abs);
+    bool any = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float f0 = floorf((p[a] - r - mg - hdr->dom_lo[a]) * hdr->cell_inv[a]);
+        const float f1 = floorf((p[a] + r + mg - hdr->dom_lo[a]) * hdr->cell_inv[a]);
+        const float dm = (float)(hdr->dims[a] - 1);
+        any = any && (f0 <= f1) && (f1 >= 0.0f) && (f0 <= dm);
+        c0[a] = (int)fminf(fmaxf(f0, 0.0f), dm);
+        c1[a] = (int)fminf(fmaxf(f1, 0.0f), dm);
+    }
+    return any;
+}
 
+struct Lds {
+    float4 slot[NG][WAVE];        // lane-private S, comp S, Q, comp Q per group
+    float4 part[2][WAVE];         // lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
+    uint32_t rs[WAVE];            // row start in the payload
+    uint32_t ro[WAVE];            // row offset in the concatenation (exclusive)
+    uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
+    uint32_t hist[RHIST_BINS];
+};
+
+template <int G, bool NRM, bool VCM>
+__device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, bool active, uint64_t &pairs_acc,
+                                        uint64_t &cand_acc)
+{
     const int lane = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t q = (int64_t)tile * TILE + lane;
-    const bool active = q < A.H;
-    SetHeader *hdr = A.hdr;
-    const int64_t ps = A.pstride;
+    const int j = lane % G;
+    const int base = lane - j;
+    const SetHeader *hdr = A.hdr;
 
-    float x = 0.0f, y = 0.0f, z = 0.0f, r = 0.0f;
-    float nx = 0.0f, ny = 0.0f, nz = 1.0f, ux = 1.0f, uy = 0.0f, uz = 0.0f, vx = 0.0f, vy = 1.0f, vz = 0.0f;
+    float p[3] = {0.0f, 0.0f, 0.0f}, nv[3] = {0.0f, 0.0f, 1.0f}, u[3] = {1.0f, 0.0f, 0.0f}, v[3] = {0.0f, 1.0f, 0.0f};
+    float r = 0.0f;
     if (active) {
-        x = A.kp[0][q];
-        y = A.kp[1][q];
-        z = A.kp[2][q];
-        r = A.r[q];
-        ux = A.ku[0][q];
-        uy = A.ku[1][q];
-        uz = A.ku[2][q];
-        vx = A.kv[0][q];
-        vy = A.kv[1][q];
-        vz = A.kv[2][q];
-        if (NRM) {
-            nx = A.kn[0][q];
-            ny = A.kn[1][q];
-            nz = A.kn[2][q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = A.kp[a][q];
+            u[a] = A.ku[a][q];
+            v[a] = A.kv[a][q];
+            if (NRM) nv[a] = A.kn[a][q];
         }
+        r = A.r[q];
     }
     const float r2 = active ? r * r : -1.0f;
     float inv_eta = 0.0f, wc = 0.0f, cbR = 0.0f, cbG = 0.0f, cbB = 0.0f;
@@ -106,85 +119,61 @@ __global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
         cbB = A.cb[2][q];
     }
 #pragma unroll
-    for (int g = 0; g < NG; ++g)
-        slot[g][lane] = active ? make_float4(A.sq[4 * g][q], A.sq[4 * g + 1][q], A.sq[4 * g + 2][q], A.sq[4 * g + 3][q])
-                               : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    lhist[lane] = 0;
-
+    for (int g = 0; g < NG; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float fR = 0.0f, cR = 0.0f, fG = 0.0f, cG = 0.0f, fB = 0.0f, cB = 0.0f;
-    uint32_t cnt = 0;
-    unsigned long long visited = 0;      // photons staged for this tile (wave-uniform)
+    uint32_t cnt = 0, ncand = 0;
 
-    // union of the tile's disks, grown by a rounding margin, as a box of grid cells
-    const float mg = active ? fmaf(r, 1e-4f, hdr->margin_abs) : 0.0f;
-    const float p3[3] = {x, y, z};
-    int c0[3], c1[3];
-    bool any = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float lo = wave_min(active ? p3[a] - r - mg : INFINITY);
-        const float hi = wave_max(active ? p3[a] + r + mg : -INFINITY);
-        const float f0 = floorf((lo - hdr->dom_lo[a]) * hdr->cell_inv[a]);
-        const float f1 = floorf((hi - hdr->dom_lo[a]) * hdr->cell_inv[a]);
-        const float dm = (float)(hdr->dims[a] - 1);
-        if (!(f0 <= f1)) any = false;
-        c0[a] = (int)fminf(fmaxf(f0, 0.0f), dm);
-        c1[a] = (int)fminf(fmaxf(f1, 0.0f), dm);
-    }
+    int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+    const bool any = active && stencil(hdr, p, r, c0, c1);
     const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
     const int nrows = any ? nyr * nzr : 0;
-    const int dimx = hdr->dims[0], dimy = hdr->dims[1];
+    const uint32_t dimx = (uint32_t)hdr->dims[0], dimy = (uint32_t)hdr->dims[1];
+    const int nbatch = wave_max_i((nrows + G - 1) / G);
 
-    for (int rb = 0; rb < nrows; rb += 64) {
-        const int row = rb + lane;
+    for (int b = 0; b < nbatch; ++b) {
+        const int row = b * G + j;
         uint32_t st = 0, len = 0;
         if (row < nrows) {
-            const int cy = c0[1] + row % nyr, cz = c0[2] + row / nyr;
-            const uint32_t base = ((uint32_t)cz * (uint32_t)dimy + (uint32_t)cy) * (uint32_t)dimx;
-            st = A.cstart[base + (uint32_t)c0[0]];
-            len = A.cstart[base + (uint32_t)c1[0] + 1u] - st;
+            const uint32_t cy = (uint32_t)(c0[1] + row % nyr), cz = (uint32_t)(c0[2] + row / nyr);
+            const uint32_t cell = (cz * dimy + cy) * dimx;
+            st = A.cstart[cell + (uint32_t)c0[0]];
+            len = A.cstart[cell + (uint32_t)c1[0] + 1u] - st;
         }
-        const uint32_t inc = wave_incl_scan_u32(len);
-        const uint32_t total = __shfl(inc, 63, 64);
+        const uint32_t inc = group_incl_scan<G>(len, j);
+        const uint32_t total = __shfl(inc, base + G - 1, WAVE);
         __syncthreads();
-        rstart[lane] = st;
-        roff[lane] = (row < nrows) ? inc - len : total;
+        L.rs[lane] = st;
+        L.ro[lane] = inc - len;
+        L.re[lane] = inc;
         __syncthreads();
-        for (uint32_t v0 = 0; v0 < total; v0 += CHUNK) {
-            const uint32_t v = v0 + lane;
-            if (v < total) {
-                int j = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1)
-                    if (roff[j + step] <= v) j += step;
-                const int64_t p = (int64_t)rstart[j] + (v - roff[j]);
-                chA[lane] = make_float4(A.pay[0 * ps + p], A.pay[1 * ps + p], A.pay[2 * ps + p], A.pay[9 * ps + p]);
-                if (NRM) chN[lane] = make_float4(A.pay[3 * ps + p], A.pay[4 * ps + p], A.pay[5 * ps + p], 0.0f);
-                chF[lane] = make_float4(A.pay[6 * ps + p], A.pay[7 * ps + p], A.pay[8 * ps + p],
-                                        VCM ? A.pay[10 * ps + p] : 0.0f);
-                if (VCM) chM[lane] = A.pay[11 * ps + p];
-            }
-            __syncthreads();
-            const int nv = (int)min((uint32_t)CHUNK, total - v0);
-            visited += (unsigned long long)nv;
-            for (int k = 0; k < nv; ++k) {
-                const float4 a = chA[k];
-                const float dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        const int nsteps = wave_max_i((int)((total + G - 1) / G));
+        int cur = 0;
+        for (int s = 0; s < nsteps; ++s) {
+            const uint32_t vi = (uint32_t)(s * G + j);
+            if (vi < total) {
+                while (vi >= L.re[base + cur]) ++cur;
+                const int64_t pi = (int64_t)L.rs[base + cur] + (vi - L.ro[base + cur]);
+                ++ncand;
+                const float4 a = A.payA[pi];
+                const float dx = p[0] - a.x, dy = p[1] - a.y, dz = p[2] - a.z;
                 const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 bool in = d2 < r2;
+                float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+                if (NRM || VCM) {
+                    if (in) bN = A.payB[pi];
+                }
                 if (NRM) {
-                    const float4 nn = chN[k];
-                    const float c = fmaf(nz, nn.z, fmaf(ny, nn.y, nx * nn.x));
+                    const float c = fmaf(nv[2], bN.z, fmaf(nv[1], bN.y, nv[0] * bN.x));
                     in = in && (c >= A.cos_min);
                 }
                 if (in) {
-                    const float yu = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
-                    const float yv = fmaf(dz, vz, fmaf(dy, vy, dx * vx));
+                    const float4 f = A.payC[pi];
+                    const float yu = fmaf(dz, u[2], fmaf(dy, u[1], dx * u[0]));
+                    const float yv = fmaf(dz, v[2], fmaf(dy, v[1], dx * v[0]));
                     const int g = group_of(yu, yv, d2, r2);
-                    const float4 f = chF[k];
                     float psi, wR, wG, wB;
                     if (VCM) {
-                        const float wl = fmaf(chM[k], INV_PI_F, f.w * inv_eta);
+                        const float wl = fmaf(bN.w, INV_PI_F, f.w * inv_eta);
                         const float w = 1.0f / ((1.0f + wl) + wc);
                         const float yl = fmaf(0.0722f, cbB * f.z, fmaf(0.7152f, cbG * f.y, 0.2126f * (cbR * f.x)));
                         psi = w * yl;
@@ -197,109 +186,191 @@ __global__ __launch_bounds__(TILE) void gather_update_kernel(GatherArgs A)
                         wG = f.y;
                         wB = f.z;
                     }
-                    float4 s = slot[g][lane];
-                    kahan(s.x, s.y, psi);
-                    kahan(s.z, s.w, psi * psi);
-                    slot[g][lane] = s;
+                    float4 sv = L.slot[g][lane];
+                    kahan(sv.x, sv.y, psi);
+                    kahan(sv.z, sv.w, psi * psi);
+                    L.slot[g][lane] = sv;
                     kahan(fR, cR, wR);
                     kahan(fG, cG, wG);
                     kahan(fB, cB, wB);
                     ++cnt;
                 }
             }
-            __syncthreads();
         }
     }
 
-    if (active) {
-        const uint32_t t_new = A.t[q] + 1u;
-        const uint32_t seen = A.nseen[q] + cnt;
-        const double m = A.mprefix[A.iter] - A.mprefix[A.iter - (int)t_new];
-        double S[NG], Q[NG], tot = 0.0;
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            const float4 s = slot[g][lane];
-            S[g] = (double)s.x - (double)s.y;
-            Q[g] = (double)s.z - (double)s.w;
-            tot += S[g];
+    // combine the G lane partials in lane order: lane j < 12 sums group j, lanes 12 and 13 the flux
+    L.part[0][lane] = make_float4(fR, cR, fG, cG);
+    L.part[1][lane] = make_float4(fB, cB, 0.0f, 0.0f);
+    __syncthreads();
+    float S = 0.0f, cS = 0.0f, Q = 0.0f, cQ = 0.0f;
+    if (active && j < NG) {
+        S = A.sq[4 * j][q];
+        cS = A.sq[4 * j + 1][q];
+        Q = A.sq[4 * j + 2][q];
+        cQ = A.sq[4 * j + 3][q];
+    }
+    if (j < NG + 2) {
+        for (int l = 0; l < G; ++l) {
+            const float4 x = (j < NG) ? L.slot[j][base + l] : L.part[j - NG][base + l];
+            kahan(S, cS, x.x);
+            kahan(S, cS, -x.y);
+            kahan(Q, cQ, x.z);
+            kahan(Q, cQ, -x.w);
         }
-        double ssb = 0.0, ssw = 0.0;
-        const double mean = tot / NG;
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            const double d = S[g] - mean;
-            ssb += d * d;
-            ssw += Q[g] - S[g] * S[g] / m;
-        }
-        ssb /= m;
+    }
+    const uint32_t cnt_q = group_sum_u<G>(cnt);
+    const uint32_t t_new = active ? A.t[q] + 1u : 1u;
+    const double m = active ? A.mprefix[A.iter] - A.mprefix[A.iter - (int)t_new] : 2.0;
+    const double Sg = (j < NG) ? (double)S - (double)cS : 0.0;
+    const double Qg = (j < NG) ? (double)Q - (double)cQ : 0.0;
+    const double tot = group_sum<G>(Sg);
+    const double dmean = (j < NG) ? Sg - tot / NG : 0.0;
+    const double ssb = group_sum<G>(dmean * dmean) / m;
+    const double ssw = group_sum<G>((j < NG) ? Qg - Sg * Sg / m : 0.0);
+    const float flR = __shfl(S - cS, base + NG, WAVE);
+    const float flG = __shfl(Q - cQ, base + NG, WAVE);
+    const float flB = __shfl(S - cS, base + NG + 1, WAVE);
+
+    int shrink = 0;
+    if (active && j == 0) {
+        const uint32_t seen = A.nseen[q] + cnt_q;
         const double F = (ssb / (NG - 1)) / (ssw / (NG * (m - 1.0)));
         const double Fc = A.fctab[t_new];
-        const bool valid = seen > 0u && ssw > 0.0 && m >= 2.0;
-        const bool shrink = valid && (F > Fc);
-
+        shrink = (seen > 0u && ssw > 0.0 && m >= 2.0 && (F > Fc)) ? 1 : 0;
         // this iteration's kernel estimate with its own radius
         const float denom = A.Jf * (PI_F * r2);
-        float eR = (fR - cR) / denom, eG = (fG - cG) / denom, eB = (fB - cB) / denom;
+        float eR = flR / denom, eG = flG / denom, eB = flB / denom;
         if (VCM) {
             eR = cbR * eR;
             eG = cbG * eG;
             eB = cbB * eB;
         }
-        float tR = A.tau[0][q], tRc = A.tau[1][q], tG = A.tau[2][q], tGc = A.tau[3][q], tB = A.tau[4][q],
-              tBc = A.tau[5][q];
-        kahan(tR, tRc, eR);
-        kahan(tG, tGc, eG);
-        kahan(tB, tBc, eB);
-        A.tau[0][q] = tR;
-        A.tau[1][q] = tRc;
-        A.tau[2][q] = tG;
-        A.tau[3][q] = tGc;
-        A.tau[4][q] = tB;
-        A.tau[5][q] = tBc;
-
-        const float rn = shrink ? fmaxf(A.k * r, A.lb) : r;
+        float tv[6];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            const float4 s = shrink ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : slot[g][lane];
-            A.sq[4 * g][q] = s.x;
-            A.sq[4 * g + 1][q] = s.y;
-            A.sq[4 * g + 2][q] = s.z;
-            A.sq[4 * g + 3][q] = s.w;
-        }
+        for (int c = 0; c < 6; ++c) tv[c] = A.tau[c][q];
+        kahan(tv[0], tv[1], eR);
+        kahan(tv[2], tv[3], eG);
+        kahan(tv[4], tv[5], eB);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A.tau[c][q] = tv[c];
+        const float rn = shrink ? fmaxf(A.k * r, A.lb) : r;
         A.r[q] = rn;
         A.t[q] = shrink ? 0u : t_new;
         A.nseen[q] = shrink ? 0u : seen;
-        A.cnt[q] = cnt;
+        A.cnt[q] = cnt_q;
         A.dec[q] = shrink ? 1u : 0u;
         A.F[q] = seen > 0u ? F : (double)NAN;
         A.Fc[q] = Fc;
-        atomicAdd(&lhist[radius_bin(rn, A.r1)], 1u);
+        atomicAdd(&L.hist[radius_bin(rn, A.r1)], 1u);
+    }
+    shrink = __shfl(shrink, base, WAVE);
+    if (active && j < NG) {
+        A.sq[4 * j][q] = shrink ? 0.0f : S;
+        A.sq[4 * j + 1][q] = shrink ? 0.0f : cS;
+        A.sq[4 * j + 2][q] = shrink ? 0.0f : Q;
+        A.sq[4 * j + 3][q] = shrink ? 0.0f : cQ;
+    }
+    pairs_acc += cnt;
+    cand_acc += ncand;
+    __syncthreads();
+}
+
+template <bool NRM, bool VCM>
+__global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
+{
+    __shared__ Lds L;
+    const int lane = threadIdx.x;
+    L.hist[lane] = 0;
+    __syncthreads();
+    constexpr uint32_t KPW = WAVE / G_LIGHT;     // light kernels per wave
+    const uint32_t n_heavy = A.counts[0], n_light = A.counts[1];
+    const uint32_t n_items = n_heavy + (n_light + KPW - 1) / KPW;
+    uint64_t pairs = 0, cand = 0;
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        if (item < n_heavy) {
+            process<G_HEAVY, NRM, VCM>(A, L, (int64_t)A.heavy[item], true, pairs, cand);
+        } else {
+            const uint32_t li = (item - n_heavy) * KPW + (uint32_t)(lane / G_LIGHT);
+            const bool act = li < n_light;
+            const int64_t q = act ? (int64_t)A.light[li] : 0;
+            process<G_LIGHT, NRM, VCM>(A, L, q, act, pairs, cand);
+        }
     }
     __syncthreads();
-    if (lhist[lane]) atomicAdd(&hdr->rhist[lane], lhist[lane]);
-    // tile totals for throughput accounting: in-disk pairs and lane x photon tests
-    unsigned long long pairs = cnt;
+    if (L.hist[lane]) atomicAdd(&A.hdr->rhist[lane], L.hist[lane]);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
-    const unsigned long long nact = (unsigned long long)__popcll(__ballot(active));
+    for (int o = 32; o > 0; o >>= 1) {
+        pairs += __shfl_xor(pairs, o, WAVE);
+        cand += __shfl_xor(cand, o, WAVE);
+    }
     if (lane == 0) {
-        atomicAdd(&hdr->n_pairs, pairs);
-        atomicAdd(&hdr->n_cand, visited * nact);
-        if (blockIdx.x == 0) atomicAdd(&hdr->n_launch, 1ull);
+        if (pairs) atomicAdd(&A.hdr->n_pairs, (unsigned long long)pairs);
+        if (cand) atomicAdd(&A.hdr->n_cand, (unsigned long long)cand);
+        if (blockIdx.x == 0) atomicAdd(&A.hdr->n_launch, 1ull);
     }
 }
 
 void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)
 {
-    if (a.ntiles <= 0) return;
+    if (a.H <= 0) return;
+    const int grid = (int)cdiv(a.H, WAVE / G_LIGHT);
     if (nrm && vcm)
-        gather_update_kernel<true, true><<<a.ntiles, TILE, 0, s>>>(a);
+        gather_update_kernel<true, true><<<grid, WAVE, 0, s>>>(a);
     else if (nrm)
-        gather_update_kernel<true, false><<<a.ntiles, TILE, 0, s>>>(a);
+        gather_update_kernel<true, false><<<grid, WAVE, 0, s>>>(a);
     else if (vcm)
-        gather_update_kernel<false, true><<<a.ntiles, TILE, 0, s>>>(a);
+        gather_update_kernel<false, true><<<grid, WAVE, 0, s>>>(a);
     else
-        gather_update_kernel<false, false><<<a.ntiles, TILE, 0, s>>>(a);
+        gather_update_kernel<false, false><<<grid, WAVE, 0, s>>>(a);
+}
+
+// ------------------------------------------------------------------------------------------------
+// work list: cost of a kernel = photons in its stencil; heavy kernels (cost > heavy_cost) first
+// ------------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= l.H) return;
+    const float p[3] = {l.kp[0][q], l.kp[1][q], l.kp[2][q]};
+    int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+    uint32_t cost = 0;
+    if (stencil(l.hdr, p, l.r[q], c0, c1)) {
+        const uint32_t dimx = (uint32_t)l.hdr->dims[0], dimy = (uint32_t)l.hdr->dims[1];
+        for (int cz = c0[2]; cz <= c1[2]; ++cz)
+            for (int cy = c0[1]; cy <= c1[1]; ++cy) {
+                const uint32_t cell = ((uint32_t)cz * dimy + (uint32_t)cy) * dimx;
+                cost += l.cstart[cell + (uint32_t)c1[0] + 1u] - l.cstart[cell + (uint32_t)c0[0]];
+            }
+    }
+    const uint32_t h = cost > l.heavy_cost ? 1u : 0u;
+    l.flag[q] = h;
+    l.offs[q] = h;
+}
+
+__global__ __launch_bounds__(256) void split_kernel(ListLaunch l)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= l.H) return;
+    const uint32_t o = l.offs[q];
+    if (l.flag[q])
+        l.heavy[o] = (uint32_t)q;
+    else
+        l.light[(uint32_t)q - o] = (uint32_t)q;
+    if (q == l.H - 1) {
+        const uint32_t nh = o + l.flag[q];
+        l.counts[0] = nh;
+        l.counts[1] = (uint32_t)l.H - nh;
+    }
+}
+
+void build_work_list(const ListLaunch &l, hipStream_t s)
+{
+    const int nb = (int)cdiv(l.H, 256);
+    cost_kernel<<<nb, 256, 0, s>>>(l);
+    excl_scan(l.offs, l.H, l.part2, s);
+    split_kernel<<<nb, 256, 0, s>>>(l);
 }
 
 // ------------------------------------------------------------------------------------------------

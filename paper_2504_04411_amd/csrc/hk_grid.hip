@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len
     }
 }
 
-static void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s)
+void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s)
 {
     const int nparts = (int)cdiv(len, SCAN_TILE);
     scan_reduce_kernel<<<nparts, 256, 0, s>>>(d, len, part);
@@ -257,29 +257,21 @@ __global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const f
     if (q < n) keys[q] = cell_key(hdr, px[q], py[q], pz[q]);
 }
 
-__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *sval, float *pay,
+__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *sval, float4 *pay,
                                                       int64_t ps)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const uint32_t j = sval[q];
     const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
-    pay[0 * ps + q] = src.pos[0][j];
-    pay[1 * ps + q] = src.pos[1][j];
-    pay[2 * ps + q] = src.pos[2][j];
-    if (src.nrm[0]) {
-        pay[3 * ps + q] = src.nrm[0][j];
-        pay[4 * ps + q] = src.nrm[1][j];
-        pay[5 * ps + q] = src.nrm[2][j];
-    }
-    pay[6 * ps + q] = R;
-    pay[7 * ps + q] = G;
-    pay[8 * ps + q] = B;
-    pay[9 * ps + q] = luminance(R, G, B);
-    if (src.mis[0]) {
-        pay[10 * ps + q] = src.mis[0][j];
-        pay[11 * ps + q] = src.mis[2][j];
-    }
+    const float dvcm = src.mis[0] ? src.mis[0][j] : 0.0f;
+    const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
+    pay[q] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
+    if (src.nrm[0])
+        pay[ps + q] = make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm);
+    else
+        pay[ps + q] = make_float4(0.0f, 0.0f, 1.0f, dvm);
+    pay[2 * ps + q] = make_float4(R, G, B, dvcm);
 }
 
 __global__ __launch_bounds__(256) void cstart_kernel(const SetHeader *hdr, const uint32_t *skeys, int64_t n,

@@ -13,8 +13,9 @@ constexpr int NSQ = 4 * NG;         // per group: S, comp(S), Q, comp(Q)
 constexpr int RHIST_BINS = 64;      // radius histogram: bin = floor(-4 log2(r / r1))
 constexpr uint32_t KEY_OUTSIDE = 0xFFFFFFu;   // cell key of a photon outside the grid domain
 constexpr uint32_t MAX_CELLS = 0xFFFFF0u;     // keys fit 24 bits: three 8-bit radix passes
-constexpr int TILE = 64;            // kernels per gather tile (one wavefront, one lane per kernel)
-constexpr int CHUNK = 64;           // photons staged in LDS per step
+constexpr int WAVE = 64;            // wavefront width of gfx950
+constexpr int G_LIGHT = 16;         // lanes per kernel in a light work item (4 kernels per wave)
+constexpr int G_HEAVY = 64;         // lanes per kernel in a heavy work item (1 kernel per wave)
 constexpr float PI_F = 3.14159265358979323846f;
 constexpr float INV_PI_F = 0.31830988618379067f;
 
@@ -141,8 +142,8 @@ inline StateView make_view(void *base, const Layout &L)
 struct WsLayout {
     int64_t max_photons = 0, max_kernels = 0;
     uint32_t max_cells = 0;
-    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, cstart = 0, pay = 0, tiles = 0;
-    int n_pay = 0;
+    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, cstart = 0, pay = 0;
+    size_t flag = 0, offs = 0, part2 = 0, heavy = 0, light = 0, counts = 0;
     size_t total = 0;
 };
 
@@ -150,7 +151,8 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // keys per radix block
 constexpr int SCAN_TILE = 4096;                    // counters per scan block
-constexpr int N_PAY = 13;   // sorted payload: pos 3, nrm 3, flux/throughput 3, psi/lum 1, dVCM, dVM, spare
+// sorted payload, three float4 per photon: (x, y, z, luminance), (nx, ny, nz, dVM), (R, G, B, dVCM)
+constexpr int PAY_VEC = 3;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -174,9 +176,14 @@ inline WsLayout make_ws_layout(int64_t max_photons, int64_t max_kernels)
     W.hist = take(4 * (size_t)(256 * nblk));
     W.part = take(4 * (size_t)(cdiv(256 * nblk, SCAN_TILE) + 1));
     W.cstart = take(4 * (size_t)(W.max_cells + 2));
-    W.n_pay = N_PAY;
-    W.pay = take(4 * (size_t)max_photons * N_PAY + 256);
-    W.tiles = take(16 * (size_t)(cdiv(max_kernels, TILE) + 1));
+    W.pay = take(16 * (size_t)max_photons * PAY_VEC + 256);
+    const size_t hk = 4 * (size_t)(max_kernels + 1);
+    W.flag = take(hk);
+    W.offs = take(hk);
+    W.part2 = take(4 * (size_t)(cdiv(max_kernels + 1, SCAN_TILE) + 1));
+    W.heavy = take(hk);
+    W.light = take(hk);
+    W.counts = take(64);
     W.total = off;
     return W;
 }

@@ -24,7 +24,7 @@ struct GridLaunch {
     PhotonSrc src;
     int64_t n;
     uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *cstart;
-    float *pay;
+    float4 *pay;             // payload, PAY_VEC float4 rows of pstride photons
     int64_t pstride;
     uint32_t ncells_bound;   // cells of the plan never exceed this (workspace capacity)
 };
@@ -43,11 +43,9 @@ struct InitLaunch {
 // Everything the fused gather / test / update kernel reads or writes for one set.
 struct GatherArgs {
     int64_t H;
-    int ntiles;
     SetHeader *hdr;
     const uint32_t *cstart;
-    const float *pay;
-    int64_t pstride;
+    const float4 *payA, *payB, *payC;
     const float *kp[3], *kn[3], *ku[3], *kv[3];
     float *r;
     uint32_t *t, *nseen, *cnt, *dec;
@@ -62,6 +60,19 @@ struct GatherArgs {
     float k;
     float cos_min;
     float r1;
+    // work list: heavy kernels (one per wave, 64 lanes) first, then light kernels (16 lanes each)
+    const uint32_t *heavy, *light, *counts;
+};
+
+// Work-list construction for one set's gather.
+struct ListLaunch {
+    int64_t H;
+    const SetHeader *hdr;
+    const uint32_t *cstart;
+    const float *kp[3];
+    const float *r;
+    uint32_t heavy_cost;
+    uint32_t *flag, *offs, *part2, *heavy, *light, *counts;
 };
 
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
@@ -72,6 +83,8 @@ void launch_plan(SetHeader *hdr, double *mprefix, int iter, double J, float cell
                  uint32_t max_cells, hipStream_t s);
 void launch_fcrit(double *fctab, const double *mprefix, int iter, int t_lo, int t_hi, double alpha_f,
                   hipStream_t s);
+void build_work_list(const ListLaunch &l, hipStream_t s);
 void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s);
+void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s);
 
 }  // namespace hk
