@@ -118,7 +118,8 @@ int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *const pos[3]
 /* Runs one iteration (steps 1-6 above) for each of the n_sets sets; ph[s] holds set s's light
  * vertices and state[s] its state, set_ids[s] its id. Sets run one after the other on `stream`.
  * `workspace` (device, workspace_bytes long) must hold hk_workspace_bytes(ctx, n_stored, H) for
- * every set (HK_E_SMALL_BUFFER otherwise). Arguments of all sets are checked before any work is
+ * every set (HK_E_SMALL_BUFFER otherwise); a set holds at most 2^27 - 1 stored light vertices per
+ * iteration (HK_E_UNSUPPORTED). Arguments of all sets are checked before any work is
  * enqueued. Non-finite photon values are not rejected: a NaN position never lands in a disk, a NaN
  * flux makes that kernel's F NaN, which keeps the radius (IEEE comparison). */
 int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,

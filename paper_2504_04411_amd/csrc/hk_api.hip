@@ -237,6 +237,8 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         if (P.J_emitted < 1 || P.n_stored < 0 || (uint64_t)P.n_stored > P.J_emitted)
             return fail(HK_E_INVALID_ARG, "set %d: need 1 <= J_emitted and 0 <= n_stored <= J_emitted", id);
         if (P.J_emitted > (uint64_t)1 << 52) return fail(HK_E_INVALID_ARG, "J_emitted too large");
+        if (P.n_stored >= ((int64_t)1 << 27))
+            return fail(HK_E_UNSUPPORTED, "set %d: at most 2^27 - 1 stored light vertices per set", id);
         if (P.n_stored > 0) {
             for (int a = 0; a < 3; ++a)
                 if (!P.pos[a] || !P.flux[a]) return fail(HK_E_INVALID_ARG, "set %d: pos/flux is NULL", id);
@@ -319,6 +321,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         a.payA = g.pay;
         a.payB = g.pay + g.pstride;
         a.payC = g.pay + 2 * g.pstride;
+        a.npay = (uint32_t)P.n_stored;
         a.heavy = wl.heavy;
         a.light = wl.light;
         a.counts = wl.counts;

@@ -61,6 +61,13 @@ __device__ __forceinline__ uint32_t group_sum_u(uint32_t v)
     return v;
 }
 
+// 16-byte load at a wave-uniform base plus a 32-bit byte offset (global_load with an SGPR base: no
+// 64-bit address arithmetic per lane; payload planes stay below 4 GiB).
+__device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (idx << 4));
+}
+
 // Grid cells overlapping [p - r - margin, p + r + margin] on every axis; false if none.
 __device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], float r, int c0[3], int c1[3])
 {
@@ -95,6 +102,7 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
     const int j = lane % G;
     const int base = lane - j;
     const SetHeader *hdr = A.hdr;
+    const float4 *rA = A.payA, *rB = A.payB, *rC = A.payC;
 
     float p[3] = {0.0f, 0.0f, 0.0f}, nv[3] = {0.0f, 0.0f, 1.0f}, u[3] = {1.0f, 0.0f, 0.0f}, v[3] = {0.0f, 1.0f, 0.0f};
     float r = 0.0f;
@@ -147,27 +155,53 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         L.re[lane] = inc;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
+        // per-lane cursor over the concatenated rows: photon index = virtual index + delta of its row
         int cur = 0;
+        uint32_t row_end = L.re[base];
+        uint32_t delta = L.rs[base] - L.ro[base];
+        uint32_t vi = (uint32_t)j;
+        bool val_n = vi < total;
+        uint32_t pi_n = 0;
+        float4 a_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (val_n) {
+            while (vi >= row_end) {
+                ++cur;
+                row_end = L.re[base + cur];
+                delta = L.rs[base + cur] - L.ro[base + cur];
+            }
+            pi_n = vi + delta;
+            a_n = ld4(rA, pi_n);
+        }
         for (int s = 0; s < nsteps; ++s) {
-            const uint32_t vi = (uint32_t)(s * G + j);
-            if (vi < total) {
-                while (vi >= L.re[base + cur]) ++cur;
-                const int64_t pi = (int64_t)L.rs[base + cur] + (vi - L.ro[base + cur]);
+            const bool val = val_n;
+            const uint32_t pi = pi_n;
+            const float4 a = a_n;
+            vi += G;
+            val_n = vi < total;
+            if (val_n) {                      // issue the next photon's load before using this one
+                while (vi >= row_end) {
+                    ++cur;
+                    row_end = L.re[base + cur];
+                    delta = L.rs[base + cur] - L.ro[base + cur];
+                }
+                pi_n = vi + delta;
+                a_n = ld4(rA, pi_n);
+            }
+            if (val) {
                 ++ncand;
-                const float4 a = A.payA[pi];
                 const float dx = p[0] - a.x, dy = p[1] - a.y, dz = p[2] - a.z;
                 const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 bool in = d2 < r2;
                 float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
                 if (NRM || VCM) {
-                    if (in) bN = A.payB[pi];
+                    if (in) bN = ld4(rB, pi);
                 }
                 if (NRM) {
                     const float c = fmaf(nv[2], bN.z, fmaf(nv[1], bN.y, nv[0] * bN.x));
                     in = in && (c >= A.cos_min);
                 }
                 if (in) {
-                    const float4 f = A.payC[pi];
+                    const float4 f = ld4(rC, pi);
                     const float yu = fmaf(dz, u[2], fmaf(dy, u[1], dx * u[0]));
                     const float yv = fmaf(dz, v[2], fmaf(dy, v[1], dx * v[0]));
                     const int g = group_of(yu, yv, d2, r2);

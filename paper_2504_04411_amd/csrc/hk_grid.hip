@@ -5,7 +5,8 @@
 //   keys      cell index of every photon (x fastest), KEY_OUTSIDE outside the grid domain
 //   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
 //             a three-phase exclusive scan and a wave-ballot stable scatter
-//   permute   sorted structure-of-arrays payload copy (and the photon's luminance for PPM)
+//   permute   inverse permutation, then a coalesced read / scattered write of the photon payload
+//             into sorted order (three float4 per photon, with the photon's luminance for PPM)
 //   cstart    cstart[c] = first sorted position with key >= c, for c in [0, ncells]
 #include <math.h>
 
@@ -257,12 +258,20 @@ __global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const f
     if (q < n) keys[q] = cell_key(hdr, px[q], py[q], pz[q]);
 }
 
-__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *sval, float4 *pay,
-                                                      int64_t ps)
+// inv[original index] = sorted position
+__global__ __launch_bounds__(256) void invert_kernel(const uint32_t *sval, int64_t n, uint32_t *inv)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= n) return;
-    const uint32_t j = sval[q];
+    if (q < n) inv[sval[q]] = (uint32_t)q;
+}
+
+// Reads the input photons in their own order (coalesced) and writes each to its sorted position.
+__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *pay,
+                                                      int64_t ps)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t q = inv[j];
     const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
     const float dvcm = src.mis[0] ? src.mis[0][j] : 0.0f;
     const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
@@ -300,7 +309,9 @@ void build_grid(const GridLaunch &g, hipStream_t s)
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
         uint32_t *ks, *vs;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &vs);
-        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, vs, g.pay, g.pstride);
+        uint32_t *inv = (vs == g.valA) ? g.valB : g.valA;
+        invert_kernel<<<nb, 256, 0, s>>>(vs, n, inv);
+        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pstride);
         cstart_kernel<<<(int)cdiv(n + 1, 256), 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     } else {
         cstart_zero_kernel<<<(int)cdiv((int64_t)g.ncells_bound + 1, 256), 256, 0, s>>>(g.hdr, g.cstart,

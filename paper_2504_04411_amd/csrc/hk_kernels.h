@@ -46,6 +46,7 @@ struct GatherArgs {
     SetHeader *hdr;
     const uint32_t *cstart;
     const float4 *payA, *payB, *payC;
+    uint32_t npay;           // photons in each payload plane (< 2^28: 32-bit byte offsets)
     const float *kp[3], *kn[3], *ku[3], *kv[3];
     float *r;
     uint32_t *t, *nseen, *cnt, *dec;
