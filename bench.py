@@ -137,7 +137,7 @@ def main():
     achieved = ops / gather_s / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-            "kernel": "gather_update_kernel<true,false>", "avg_launch_ms": round(launch_ms, 4),
+            "kernel": "gather_update_kernel<true,false,8,64>", "avg_launch_ms": round(launch_ms, 4),
             "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
     out = {
         "metric": "photon-kernel queries/sec (gather+F-test+update) at 1 GPU",

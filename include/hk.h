@@ -74,9 +74,10 @@ typedef struct hk_params {
     int32_t max_iters;     /* iterations a set may run (sizes the critical-value table), 1..65536 */
     float cell_scale;      /* grid cell = cell_scale * (radius quantile); 0 selects the default */
     float cell_quantile;   /* radius quantile in (0, 1] used for the cell size; 0 selects the default */
-    int32_t heavy_cost;    /* kernels whose grid stencil holds more photons get a wavefront of their
-                              own; 0 selects the default (4096) */
-    int32_t reserved[7];
+    int32_t heavy_cost;    /* kernels whose grid stencil holds more photons are heavy; 0: default */
+    int32_t lanes_light;   /* lanes of a wavefront per light kernel: 4, 8 or 16; 0: default */
+    int32_t lanes_heavy;   /* lanes of a wavefront per heavy kernel: 16 or 64; 0: default */
+    int32_t reserved[5];
 } hk_params;
 
 /* One iteration's light vertices of one set. */

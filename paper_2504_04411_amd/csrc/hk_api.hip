@@ -87,6 +87,8 @@ extern "C" int hk_default_params(double r1, hk_params *p)
     p->cell_scale = 1.0f;
     p->cell_quantile = 0.5f;
     p->heavy_cost = 4096;
+    p->lanes_light = 8;
+    p->lanes_heavy = 64;
     return HK_OK;
 }
 
@@ -108,12 +110,18 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
     if (p->max_iters < 1 || p->max_iters > 65536) return fail(HK_E_INVALID_ARG, "max_iters must be in [1, 65536]");
     if (!(p->cell_scale >= 0.0f && isfinite(p->cell_scale))) return fail(HK_E_INVALID_ARG, "bad cell_scale");
     if (!(p->cell_quantile >= 0.0f && p->cell_quantile <= 1.0f)) return fail(HK_E_INVALID_ARG, "bad cell_quantile");
+    if (p->lanes_light != 0 && p->lanes_light != 4 && p->lanes_light != 8 && p->lanes_light != 16)
+        return fail(HK_E_INVALID_ARG, "lanes_light must be 4, 8 or 16");
+    if (p->lanes_heavy != 0 && p->lanes_heavy != 16 && p->lanes_heavy != 64)
+        return fail(HK_E_INVALID_ARG, "lanes_heavy must be 16 or 64");
     hk_ctx *c = new (std::nothrow) hk_ctx();
     if (!c) return fail(HK_E_INVALID_ARG, "out of host memory");
     c->p = *p;
     if (c->p.cell_scale == 0.0f) c->p.cell_scale = 1.0f;
     if (c->p.cell_quantile == 0.0f) c->p.cell_quantile = 0.5f;
     if (c->p.heavy_cost <= 0) c->p.heavy_cost = 4096;
+    if (c->p.lanes_light == 0) c->p.lanes_light = 8;
+    if (c->p.lanes_heavy == 0) c->p.lanes_heavy = 64;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(HK_E_HIP, "hipGetDevice failed");
@@ -286,6 +294,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
         g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
         g.part = reinterpret_cast<uint32_t *>(w + W.part);
+        g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
         g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
         g.pay = reinterpret_cast<float4 *>(w + W.pay);
         g.pstride = P.n_stored;
@@ -325,6 +334,8 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         a.heavy = wl.heavy;
         a.light = wl.light;
         a.counts = wl.counts;
+        a.lanes_light = p.lanes_light;
+        a.lanes_heavy = p.lanes_heavy;
         for (int k = 0; k < 3; ++k) {
             a.kp[k] = st.pos[k];
             a.kn[k] = st.nrm[k];
@@ -337,8 +348,9 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         a.nseen = st.nseen;
         a.cnt = st.cnt;
         a.dec = st.dec;
-        for (int k = 0; k < NSQ; ++k) a.sq[k] = st.sq[k];
-        for (int k = 0; k < 6; ++k) a.tau[k] = st.tau[k];
+        a.sq0 = st.sq[0];
+        a.tau0 = st.tau[0];
+        a.astride = (uint32_t)(align256(sizeof(float) * (size_t)S.H) / sizeof(float));
         a.F = st.F;
         a.Fc = st.Fc;
         a.cdvcm = st.cdvcm;

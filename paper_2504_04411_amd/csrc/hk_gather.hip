@@ -7,6 +7,11 @@
 // against the disk and accumulate into lane-private compensated sums kept in LDS. At the end the
 // G partial results are combined in a fixed order (deterministic) and the kernel's epilogue runs.
 //
+// The test and the accumulation are decoupled: each step tests G candidates (one per lane), the
+// in-disk ones are queued in LDS (lane order), and whenever a kernel has G queued photons its G
+// lanes accumulate them together, so the accumulation runs with every lane busy instead of only the
+// third of lanes whose candidate fell inside the disk.
+//
 // Light kernels use G = 16 (four kernels per wave); kernels whose stencil holds more than
 // `heavy_cost` photons get a wave of their own (G = 64) and are listed first, so the longest work
 // starts first. The list is rebuilt every iteration from the grid (cost = photons in the stencil).
@@ -85,14 +90,90 @@ __device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], 
     return any;
 }
 
+constexpr int UNROLL = 4;         // candidate loads in flight per lane
+
 struct Lds {
     float4 slot[NG][WAVE];        // lane-private S, comp S, Q, comp Q per group
     float4 part[2][WAVE];         // lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
     uint32_t rs[WAVE];            // row start in the payload
     uint32_t ro[WAVE];            // row offset in the concatenation (exclusive)
     uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
+    uint32_t queue[2 * WAVE];     // in-disk photons waiting for accumulation, 2 G slots per kernel
     uint32_t hist[RHIST_BINS];
 };
+
+// Per-kernel constants of one work item, held in registers by the kernel's G lanes.
+struct Query {
+    float p[3], nv[3], u[3], v[3];
+    float r2, inv_eta, wc, cb[3];
+};
+
+// Accumulators of one lane.
+struct Acc {
+    float fR, cR, fG, cG, fB, cB;
+    uint32_t cnt, ncand;
+};
+
+// Adds the photon pi (already inside the disk) to this lane's group sums and flux sum when it
+// passes the normal-consistency test. The distance vector is recomputed from the payload with the
+// same float32 operations as in the test, so the values are those the test saw.
+template <bool NRM, bool VCM>
+__device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float cos_min, const float4 *rA,
+                                           const float4 *rB, const float4 *rC, Lds &L, int lane, Acc &c)
+{
+    const float4 a = ld4(rA, pi);
+    const float4 f = ld4(rC, pi);
+    float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+    if (NRM || VCM) bN = ld4(rB, pi);
+    if (NRM) {
+        const float cs = fmaf(K.nv[2], bN.z, fmaf(K.nv[1], bN.y, K.nv[0] * bN.x));
+        if (!(cs >= cos_min)) return;
+    }
+    const float dx = K.p[0] - a.x, dy = K.p[1] - a.y, dz = K.p[2] - a.z;
+    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float yu = fmaf(dz, K.u[2], fmaf(dy, K.u[1], dx * K.u[0]));
+    const float yv = fmaf(dz, K.v[2], fmaf(dy, K.v[1], dx * K.v[0]));
+    const int g = group_of(yu, yv, d2, K.r2);
+    float psi, wR, wG, wB;
+    if (VCM) {
+        const float wl = fmaf(bN.w, INV_PI_F, f.w * K.inv_eta);
+        const float w = 1.0f / ((1.0f + wl) + K.wc);
+        const float yl = fmaf(0.0722f, K.cb[2] * f.z, fmaf(0.7152f, K.cb[1] * f.y, 0.2126f * (K.cb[0] * f.x)));
+        psi = w * yl;
+        wR = w * f.x;
+        wG = w * f.y;
+        wB = w * f.z;
+    } else {
+        psi = a.w;
+        wR = f.x;
+        wG = f.y;
+        wB = f.z;
+    }
+    float4 sv = L.slot[g][lane];
+    kahan(sv.x, sv.y, psi);
+    kahan(sv.z, sv.w, psi * psi);
+    L.slot[g][lane] = sv;
+    kahan(c.fR, c.cR, wR);
+    kahan(c.fG, c.cG, wG);
+    kahan(c.fB, c.cB, wB);
+    ++c.cnt;
+}
+
+// Each kernel's G lanes take up to G queued photons (lane j the j-th); the rest move to the front.
+template <int G, bool NRM, bool VCM>
+__device__ __forceinline__ void drain_once(uint32_t &qlen, int j, int base, const Query &K, float cos_min,
+                                           const float4 *rA, const float4 *rB, const float4 *rC, Lds &L, int lane,
+                                           Acc &c)
+{
+    __syncthreads();
+    const uint32_t n = min(qlen, (uint32_t)G);
+    if ((uint32_t)j < n) accumulate<NRM, VCM>(L.queue[2 * base + j], K, cos_min, rA, rB, rC, L, lane, c);
+    const uint32_t rem = qlen - n;
+    const uint32_t moved = ((uint32_t)j < rem) ? L.queue[2 * base + G + j] : 0u;
+    __syncthreads();
+    if ((uint32_t)j < rem) L.queue[2 * base + j] = moved;
+    qlen = rem;
+}
 
 template <int G, bool NRM, bool VCM>
 __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, bool active, uint64_t &pairs_acc,
@@ -103,36 +184,46 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
     const int base = lane - j;
     const SetHeader *hdr = A.hdr;
     const float4 *rA = A.payA, *rB = A.payB, *rC = A.payC;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const uint64_t below = (j == 0) ? 0ull : ((~0ull >> (64 - j)) << base);
 
-    float p[3] = {0.0f, 0.0f, 0.0f}, nv[3] = {0.0f, 0.0f, 1.0f}, u[3] = {1.0f, 0.0f, 0.0f}, v[3] = {0.0f, 1.0f, 0.0f};
+    Query K;
+    for (int a = 0; a < 3; ++a) {
+        K.p[a] = 0.0f;
+        K.u[a] = (a == 0) ? 1.0f : 0.0f;
+        K.v[a] = (a == 1) ? 1.0f : 0.0f;
+        K.nv[a] = (a == 2) ? 1.0f : 0.0f;
+        K.cb[a] = 0.0f;
+    }
     float r = 0.0f;
     if (active) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            p[a] = A.kp[a][q];
-            u[a] = A.ku[a][q];
-            v[a] = A.kv[a][q];
-            if (NRM) nv[a] = A.kn[a][q];
+            K.p[a] = A.kp[a][q];
+            K.u[a] = A.ku[a][q];
+            K.v[a] = A.kv[a][q];
+            if (NRM) K.nv[a] = A.kn[a][q];
         }
         r = A.r[q];
     }
-    const float r2 = active ? r * r : -1.0f;
-    float inv_eta = 0.0f, wc = 0.0f, cbR = 0.0f, cbG = 0.0f, cbB = 0.0f;
+    K.r2 = active ? r * r : -1.0f;
+    K.inv_eta = 0.0f;
+    K.wc = 0.0f;
     if (VCM && active) {
-        const float eta = A.Jf * (PI_F * r2);       // n_VM / n_VC * pi r^2, n_VC = 1
-        inv_eta = 1.0f / eta;
-        wc = fmaf(A.cdvm[q], INV_PI_F, A.cdvcm[q] * inv_eta);
-        cbR = A.cb[0][q];
-        cbG = A.cb[1][q];
-        cbB = A.cb[2][q];
+        const float eta = A.Jf * (PI_F * K.r2);       // n_VM / n_VC * pi r^2, n_VC = 1
+        K.inv_eta = 1.0f / eta;
+        K.wc = fmaf(A.cdvm[q], INV_PI_F, A.cdvcm[q] * K.inv_eta);
+        K.cb[0] = A.cb[0][q];
+        K.cb[1] = A.cb[1][q];
+        K.cb[2] = A.cb[2][q];
     }
 #pragma unroll
     for (int g = 0; g < NG; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float fR = 0.0f, cR = 0.0f, fG = 0.0f, cG = 0.0f, fB = 0.0f, cB = 0.0f;
-    uint32_t cnt = 0, ncand = 0;
+    Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u};
+    uint32_t qlen = 0;
 
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
-    const bool any = active && stencil(hdr, p, r, c0, c1);
+    const bool any = active && stencil(hdr, K.p, r, c0, c1);
     const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
     const int nrows = any ? nyr * nzr : 0;
     const uint32_t dimx = (uint32_t)hdr->dims[0], dimy = (uint32_t)hdr->dims[1];
@@ -155,116 +246,108 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         L.re[lane] = inc;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
-        // per-lane cursor over the concatenated rows: photon index = virtual index + delta of its row
+        // Per-lane cursor over the concatenated rows: photon index = virtual index + delta of its row.
+        // Loads are issued U steps at a time (U independent 16-byte loads in flight per lane), then
+        // the U candidates are tested from registers; those inside the disk are queued.
         int cur = 0;
         uint32_t row_end = L.re[base];
         uint32_t delta = L.rs[base] - L.ro[base];
         uint32_t vi = (uint32_t)j;
-        bool val_n = vi < total;
-        uint32_t pi_n = 0;
-        float4 a_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (val_n) {
-            while (vi >= row_end) {
-                ++cur;
-                row_end = L.re[base + cur];
-                delta = L.rs[base + cur] - L.ro[base + cur];
-            }
-            pi_n = vi + delta;
-            a_n = ld4(rA, pi_n);
-        }
-        for (int s = 0; s < nsteps; ++s) {
-            const bool val = val_n;
-            const uint32_t pi = pi_n;
-            const float4 a = a_n;
-            vi += G;
-            val_n = vi < total;
-            if (val_n) {                      // issue the next photon's load before using this one
-                while (vi >= row_end) {
-                    ++cur;
-                    row_end = L.re[base + cur];
-                    delta = L.rs[base + cur] - L.ro[base + cur];
-                }
-                pi_n = vi + delta;
-                a_n = ld4(rA, pi_n);
-            }
-            if (val) {
-                ++ncand;
-                const float dx = p[0] - a.x, dy = p[1] - a.y, dz = p[2] - a.z;
-                const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                bool in = d2 < r2;
-                float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-                if (NRM || VCM) {
-                    if (in) bN = ld4(rB, pi);
-                }
-                if (NRM) {
-                    const float c = fmaf(nv[2], bN.z, fmaf(nv[1], bN.y, nv[0] * bN.x));
-                    in = in && (c >= A.cos_min);
-                }
-                if (in) {
-                    const float4 f = ld4(rC, pi);
-                    const float yu = fmaf(dz, u[2], fmaf(dy, u[1], dx * u[0]));
-                    const float yv = fmaf(dz, v[2], fmaf(dy, v[1], dx * v[0]));
-                    const int g = group_of(yu, yv, d2, r2);
-                    float psi, wR, wG, wB;
-                    if (VCM) {
-                        const float wl = fmaf(bN.w, INV_PI_F, f.w * inv_eta);
-                        const float w = 1.0f / ((1.0f + wl) + wc);
-                        const float yl = fmaf(0.0722f, cbB * f.z, fmaf(0.7152f, cbG * f.y, 0.2126f * (cbR * f.x)));
-                        psi = w * yl;
-                        wR = w * f.x;
-                        wG = w * f.y;
-                        wB = w * f.z;
-                    } else {
-                        psi = a.w;
-                        wR = f.x;
-                        wG = f.y;
-                        wB = f.z;
+        for (int s0 = 0; s0 < nsteps; s0 += UNROLL) {
+            float4 a[UNROLL];
+            uint32_t pis[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                pis[u] = 0xFFFFFFFFu;
+                a[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (vi < total) {
+                    while (vi >= row_end) {
+                        ++cur;
+                        row_end = L.re[base + cur];
+                        delta = L.rs[base + cur] - L.ro[base + cur];
                     }
-                    float4 sv = L.slot[g][lane];
-                    kahan(sv.x, sv.y, psi);
-                    kahan(sv.z, sv.w, psi * psi);
-                    L.slot[g][lane] = sv;
-                    kahan(fR, cR, wR);
-                    kahan(fG, cG, wG);
-                    kahan(fB, cB, wB);
-                    ++cnt;
+                    pis[u] = vi + delta;
+                    a[u] = ld4(rA, pis[u]);
                 }
+                vi += G;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                bool in = false;
+                if (pis[u] != 0xFFFFFFFFu) {
+                    ++c.ncand;
+                    const float dx = K.p[0] - a[u].x, dy = K.p[1] - a[u].y, dz = K.p[2] - a[u].z;
+                    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    in = d2 < K.r2;
+                }
+                // queue the in-disk photons of this step in lane order
+                const uint64_t m = __ballot(in);
+                const uint32_t before = (uint32_t)__popcll(m & below);
+                if (in) L.queue[2 * base + qlen + before] = pis[u];
+                qlen += (uint32_t)__popcll(m & gmask);
+                if (__ballot(qlen >= (uint32_t)G) != 0ull)
+                    drain_once<G, NRM, VCM>(qlen, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
             }
         }
     }
+    while (__ballot(qlen > 0u) != 0ull) drain_once<G, NRM, VCM>(qlen, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
 
-    // combine the G lane partials in lane order: lane j < 12 sums group j, lanes 12 and 13 the flux
-    L.part[0][lane] = make_float4(fR, cR, fG, cG);
-    L.part[1][lane] = make_float4(fB, cB, 0.0f, 0.0f);
+    // Combine the G lane partials in lane order. Columns 0..11 are the groups, 12 and 13 the flux
+    // pairs; lane j of the kernel combines columns j, j + G, ... (all of them in lane order).
+    L.part[0][lane] = make_float4(c.fR, c.cR, c.fG, c.cG);
+    L.part[1][lane] = make_float4(c.fB, c.cB, 0.0f, 0.0f);
     __syncthreads();
-    float S = 0.0f, cS = 0.0f, Q = 0.0f, cQ = 0.0f;
-    if (active && j < NG) {
-        S = A.sq[4 * j][q];
-        cS = A.sq[4 * j + 1][q];
-        Q = A.sq[4 * j + 2][q];
-        cQ = A.sq[4 * j + 3][q];
-    }
-    if (j < NG + 2) {
-        for (int l = 0; l < G; ++l) {
-            const float4 x = (j < NG) ? L.slot[j][base + l] : L.part[j - NG][base + l];
-            kahan(S, cS, x.x);
-            kahan(S, cS, -x.y);
-            kahan(Q, cQ, x.z);
-            kahan(Q, cQ, -x.w);
+    constexpr int COLS = NG + 2;
+    constexpr int CPL = (COLS + G - 1) / G;
+    float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int col = j + k * G;
+        S[k] = cS[k] = Q[k] = cQ[k] = 0.0f;
+        if (active && col < NG) {
+            S[k] = A.sq0[(size_t)(4 * col) * A.astride + q];
+            cS[k] = A.sq0[(size_t)(4 * col + 1) * A.astride + q];
+            Q[k] = A.sq0[(size_t)(4 * col + 2) * A.astride + q];
+            cQ[k] = A.sq0[(size_t)(4 * col + 3) * A.astride + q];
+        }
+        if (col < COLS) {
+            for (int l = 0; l < G; ++l) {
+                const float4 x = (col < NG) ? L.slot[col][base + l] : L.part[col - NG][base + l];
+                kahan(S[k], cS[k], x.x);
+                kahan(S[k], cS[k], -x.y);
+                kahan(Q[k], cQ[k], x.z);
+                kahan(Q[k], cQ[k], -x.w);
+            }
         }
     }
-    const uint32_t cnt_q = group_sum_u<G>(cnt);
+    const uint32_t cnt_q = group_sum_u<G>(c.cnt);
     const uint32_t t_new = active ? A.t[q] + 1u : 1u;
     const double m = active ? A.mprefix[A.iter] - A.mprefix[A.iter - (int)t_new] : 2.0;
-    const double Sg = (j < NG) ? (double)S - (double)cS : 0.0;
-    const double Qg = (j < NG) ? (double)Q - (double)cQ : 0.0;
-    const double tot = group_sum<G>(Sg);
-    const double dmean = (j < NG) ? Sg - tot / NG : 0.0;
-    const double ssb = group_sum<G>(dmean * dmean) / m;
-    const double ssw = group_sum<G>((j < NG) ? Qg - Sg * Sg / m : 0.0);
-    const float flR = __shfl(S - cS, base + NG, WAVE);
-    const float flG = __shfl(Q - cQ, base + NG, WAVE);
-    const float flB = __shfl(S - cS, base + NG + 1, WAVE);
+    double sg[CPL], qg[CPL];
+    double tl = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const bool grp = j + k * G < NG;
+        sg[k] = grp ? (double)S[k] - (double)cS[k] : 0.0;
+        qg[k] = grp ? (double)Q[k] - (double)cQ[k] : 0.0;
+        tl += sg[k];
+    }
+    const double tot = group_sum<G>(tl);
+    double bl = 0.0, wl = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        if (j + k * G < NG) {
+            const double d = sg[k] - tot / NG;
+            bl += d * d;
+            wl += qg[k] - sg[k] * sg[k] / m;
+        }
+    }
+    const double ssb = group_sum<G>(bl) / m;
+    const double ssw = group_sum<G>(wl);
+    constexpr int K12 = NG / G, J12 = NG % G, K13 = (NG + 1) / G, J13 = (NG + 1) % G;
+    const float flR = __shfl(S[K12] - cS[K12], base + J12, WAVE);
+    const float flG = __shfl(Q[K12] - cQ[K12], base + J12, WAVE);
+    const float flB = __shfl(S[K13] - cS[K13], base + J13, WAVE);
 
     int shrink = 0;
     if (active && j == 0) {
@@ -273,21 +356,21 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         const double Fc = A.fctab[t_new];
         shrink = (seen > 0u && ssw > 0.0 && m >= 2.0 && (F > Fc)) ? 1 : 0;
         // this iteration's kernel estimate with its own radius
-        const float denom = A.Jf * (PI_F * r2);
+        const float denom = A.Jf * (PI_F * K.r2);
         float eR = flR / denom, eG = flG / denom, eB = flB / denom;
         if (VCM) {
-            eR = cbR * eR;
-            eG = cbG * eG;
-            eB = cbB * eB;
+            eR = K.cb[0] * eR;
+            eG = K.cb[1] * eG;
+            eB = K.cb[2] * eB;
         }
         float tv[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tv[c] = A.tau[c][q];
+        for (int cc = 0; cc < 6; ++cc) tv[cc] = A.tau0[(size_t)cc * A.astride + q];
         kahan(tv[0], tv[1], eR);
         kahan(tv[2], tv[3], eG);
         kahan(tv[4], tv[5], eB);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) A.tau[c][q] = tv[c];
+        for (int cc = 0; cc < 6; ++cc) A.tau0[(size_t)cc * A.astride + q] = tv[cc];
         const float rn = shrink ? fmaxf(A.k * r, A.lb) : r;
         A.r[q] = rn;
         A.t[q] = shrink ? 0u : t_new;
@@ -299,36 +382,43 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         atomicAdd(&L.hist[radius_bin(rn, A.r1)], 1u);
     }
     shrink = __shfl(shrink, base, WAVE);
-    if (active && j < NG) {
-        A.sq[4 * j][q] = shrink ? 0.0f : S;
-        A.sq[4 * j + 1][q] = shrink ? 0.0f : cS;
-        A.sq[4 * j + 2][q] = shrink ? 0.0f : Q;
-        A.sq[4 * j + 3][q] = shrink ? 0.0f : cQ;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int col = j + k * G;
+        if (active && col < NG) {
+            A.sq0[(size_t)(4 * col) * A.astride + q] = shrink ? 0.0f : S[k];
+            A.sq0[(size_t)(4 * col + 1) * A.astride + q] = shrink ? 0.0f : cS[k];
+            A.sq0[(size_t)(4 * col + 2) * A.astride + q] = shrink ? 0.0f : Q[k];
+            A.sq0[(size_t)(4 * col + 3) * A.astride + q] = shrink ? 0.0f : cQ[k];
+        }
     }
-    pairs_acc += cnt;
-    cand_acc += ncand;
+    pairs_acc += c.cnt;
+    cand_acc += c.ncand;
     __syncthreads();
 }
 
-template <bool NRM, bool VCM>
+template <bool NRM, bool VCM, int GL, int GH>
 __global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
 {
     __shared__ Lds L;
     const int lane = threadIdx.x;
     L.hist[lane] = 0;
     __syncthreads();
-    constexpr uint32_t KPW = WAVE / G_LIGHT;     // light kernels per wave
+    constexpr uint32_t KPW_L = WAVE / GL;     // light kernels per wave
+    constexpr uint32_t KPW_H = WAVE / GH;     // heavy kernels per wave
     const uint32_t n_heavy = A.counts[0], n_light = A.counts[1];
-    const uint32_t n_items = n_heavy + (n_light + KPW - 1) / KPW;
+    const uint32_t items_h = (n_heavy + KPW_H - 1) / KPW_H;
+    const uint32_t n_items = items_h + (n_light + KPW_L - 1) / KPW_L;
     uint64_t pairs = 0, cand = 0;
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        if (item < n_heavy) {
-            process<G_HEAVY, NRM, VCM>(A, L, (int64_t)A.heavy[item], true, pairs, cand);
+        if (item < items_h) {
+            const uint32_t hi = item * KPW_H + (uint32_t)(lane / GH);
+            const bool act = hi < n_heavy;
+            process<GH, NRM, VCM>(A, L, act ? (int64_t)A.heavy[hi] : 0, act, pairs, cand);
         } else {
-            const uint32_t li = (item - n_heavy) * KPW + (uint32_t)(lane / G_LIGHT);
+            const uint32_t li = (item - items_h) * KPW_L + (uint32_t)(lane / GL);
             const bool act = li < n_light;
-            const int64_t q = act ? (int64_t)A.light[li] : 0;
-            process<G_LIGHT, NRM, VCM>(A, L, q, act, pairs, cand);
+            process<GL, NRM, VCM>(A, L, act ? (int64_t)A.light[li] : 0, act, pairs, cand);
         }
     }
     __syncthreads();
@@ -345,18 +435,36 @@ __global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
     }
 }
 
+template <bool NRM, bool VCM>
+static void launch_lanes(const GatherArgs &a, int gl, int gh, int grid, hipStream_t s)
+{
+#define HK_LAUNCH(GLV, GHV) gather_update_kernel<NRM, VCM, GLV, GHV><<<grid, WAVE, 0, s>>>(a)
+    if (gh == 16) {
+        if (gl == 4) HK_LAUNCH(4, 16);
+        else if (gl == 8) HK_LAUNCH(8, 16);
+        else HK_LAUNCH(16, 16);
+    } else {
+        if (gl == 4) HK_LAUNCH(4, 64);
+        else if (gl == 8) HK_LAUNCH(8, 64);
+        else HK_LAUNCH(16, 64);
+    }
+#undef HK_LAUNCH
+}
+
 void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)
 {
     if (a.H <= 0) return;
-    const int grid = (int)cdiv(a.H, WAVE / G_LIGHT);
+    const int gl = (a.lanes_light == 4 || a.lanes_light == 8) ? a.lanes_light : 16;
+    const int gh = (a.lanes_heavy == 16) ? 16 : 64;
+    const int grid = (int)cdiv(a.H, WAVE / gl);
     if (nrm && vcm)
-        gather_update_kernel<true, true><<<grid, WAVE, 0, s>>>(a);
+        launch_lanes<true, true>(a, gl, gh, grid, s);
     else if (nrm)
-        gather_update_kernel<true, false><<<grid, WAVE, 0, s>>>(a);
+        launch_lanes<true, false>(a, gl, gh, grid, s);
     else if (vcm)
-        gather_update_kernel<false, true><<<grid, WAVE, 0, s>>>(a);
+        launch_lanes<false, true>(a, gl, gh, grid, s);
     else
-        gather_update_kernel<false, false><<<grid, WAVE, 0, s>>>(a);
+        launch_lanes<false, false>(a, gl, gh, grid, s);
 }
 
 // ------------------------------------------------------------------------------------------------

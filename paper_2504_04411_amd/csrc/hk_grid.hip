@@ -7,7 +7,8 @@
 //             a three-phase exclusive scan and a wave-ballot stable scatter
 //   permute   inverse permutation, then a coalesced read / scattered write of the photon payload
 //             into sorted order (three float4 per photon, with the photon's luminance for PPM)
-//   cstart    cstart[c] = first sorted position with key >= c, for c in [0, ncells]
+//   cstart    photons per cell (wave-aggregated atomics on the sorted keys), exclusive scan:
+//             cstart[c] = first sorted position with key >= c, for c in [0, ncells]
 #include <math.h>
 
 #include "hk_internal.h"
@@ -283,27 +284,35 @@ __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, 
     pay[2 * ps + q] = make_float4(R, G, B, dvcm);
 }
 
-__global__ __launch_bounds__(256) void cstart_kernel(const SetHeader *hdr, const uint32_t *skeys, int64_t n,
-                                                     uint32_t *cstart)
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t n)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q > n) return;
-    const uint32_t ncells = hdr->ncells;
-    const int64_t prev = (q == 0) ? -1 : (int64_t)min(skeys[q - 1], ncells);
-    const int64_t cur = (q == n) ? (int64_t)ncells : (int64_t)min(skeys[q], ncells);
-    for (int64_t c = prev + 1; c <= cur; ++c) cstart[c] = (uint32_t)q;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
-// No photons stored: every cell is empty.
-__global__ __launch_bounds__(256) void cstart_zero_kernel(const SetHeader *hdr, uint32_t *cstart, uint32_t bound)
+// Photons per cell from the sorted keys: the first lane of every run of equal keys inside a
+// wavefront adds the run length (a handful of atomics per wavefront).
+__global__ __launch_bounds__(256) void cell_count_kernel(const SetHeader *hdr, const uint32_t *skeys, int64_t n,
+                                                         uint32_t *cnt)
 {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c <= (int64_t)hdr->ncells && c <= (int64_t)bound) cstart[c] = 0;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const uint32_t key = q < n ? skeys[q] : KEY_OUTSIDE;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool head = (lane == 0) || (key != prev);
+    const uint64_t heads = __ballot(head);
+    if (head && q < n && key < hdr->ncells) {
+        const uint64_t later = (lane == 63) ? 0ull : (heads >> (lane + 1));
+        const int next = later ? lane + 1 + __builtin_ctzll(later) : 64;
+        atomicAdd(&cnt[key], (uint32_t)(next - lane));
+    }
 }
 
 void build_grid(const GridLaunch &g, hipStream_t s)
 {
     const int64_t n = g.n;
+    const int64_t nc = (int64_t)g.ncells_bound + 1;     // counts of every possible cell, then their scan
+    zero_kernel<<<(int)cdiv(nc, 256), 256, 0, s>>>(g.cstart, nc);
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
@@ -312,11 +321,9 @@ void build_grid(const GridLaunch &g, hipStream_t s)
         uint32_t *inv = (vs == g.valA) ? g.valB : g.valA;
         invert_kernel<<<nb, 256, 0, s>>>(vs, n, inv);
         permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pstride);
-        cstart_kernel<<<(int)cdiv(n + 1, 256), 256, 0, s>>>(g.hdr, ks, n, g.cstart);
-    } else {
-        cstart_zero_kernel<<<(int)cdiv((int64_t)g.ncells_bound + 1, 256), 256, 0, s>>>(g.hdr, g.cstart,
-                                                                                       g.ncells_bound);
+        cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
+    excl_scan(g.cstart, nc, g.part3, s);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -143,7 +143,7 @@ struct WsLayout {
     int64_t max_photons = 0, max_kernels = 0;
     uint32_t max_cells = 0;
     size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, cstart = 0, pay = 0;
-    size_t flag = 0, offs = 0, part2 = 0, heavy = 0, light = 0, counts = 0;
+    size_t flag = 0, offs = 0, part2 = 0, part3 = 0, heavy = 0, light = 0, counts = 0;
     size_t total = 0;
 };
 
@@ -176,6 +176,7 @@ inline WsLayout make_ws_layout(int64_t max_photons, int64_t max_kernels)
     W.hist = take(4 * (size_t)(256 * nblk));
     W.part = take(4 * (size_t)(cdiv(256 * nblk, SCAN_TILE) + 1));
     W.cstart = take(4 * (size_t)(W.max_cells + 2));
+    W.part3 = take(4 * (size_t)(cdiv((int64_t)W.max_cells + 1, SCAN_TILE) + 1));
     W.pay = take(16 * (size_t)max_photons * PAY_VEC + 256);
     const size_t hk = 4 * (size_t)(max_kernels + 1);
     W.flag = take(hk);
@@ -214,11 +215,11 @@ __device__ __forceinline__ int group_of(float yu, float yv, float d2, float r2)
     const int ann = (d2 + d2 >= r2) ? 6 : 0;
     const float a = fmaf(-s3, yu, yv);
     const float b = fmaf(s3, yu, yv);
-    const bool upper = (yv > 0.0f) || (yv == 0.0f && yu >= 0.0f);
+    const bool upper = (yv > 0.0f) | ((yv == 0.0f) & (yu >= 0.0f));
     const int su = (a < 0.0f) ? 0 : ((b > 0.0f) ? 1 : 2);
     const int sl = (a > 0.0f) ? 3 : ((b < 0.0f) ? 4 : 5);
     int s = upper ? su : sl;
-    s = (yu == 0.0f && yv == 0.0f) ? 0 : s;
+    s = ((yu == 0.0f) & (yv == 0.0f)) ? 0 : s;
     return ann + s;
 }
 

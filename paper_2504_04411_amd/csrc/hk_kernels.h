@@ -23,7 +23,7 @@ struct GridLaunch {
     SetHeader *hdr;
     PhotonSrc src;
     int64_t n;
-    uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *cstart;
+    uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *part3, *cstart;
     float4 *pay;             // payload, PAY_VEC float4 rows of pstride photons
     int64_t pstride;
     uint32_t ncells_bound;   // cells of the plan never exceed this (workspace capacity)
@@ -50,8 +50,9 @@ struct GatherArgs {
     const float *kp[3], *kn[3], *ku[3], *kv[3];
     float *r;
     uint32_t *t, *nseen, *cnt, *dec;
-    float *sq[NSQ];
-    float *tau[6];
+    float *sq0;              // group sums: array i at sq0 + i * astride (i = 4 g + {S, comp S, Q, comp Q})
+    float *tau0;             // estimate: array c at tau0 + c * astride (R, comp R, G, comp G, B, comp B)
+    uint32_t astride;        // floats between consecutive per-kernel arrays of the state
     double *F, *Fc;
     const float *cb[3], *cdvcm, *cdvm;
     const double *fctab, *mprefix;
@@ -61,8 +62,9 @@ struct GatherArgs {
     float k;
     float cos_min;
     float r1;
-    // work list: heavy kernels (one per wave, 64 lanes) first, then light kernels (16 lanes each)
+    // work list: heavy kernels first, then light kernels; lanes per kernel for each kind
     const uint32_t *heavy, *light, *counts;
+    int lanes_light, lanes_heavy;
 };
 
 // Work-list construction for one set's gather.

@@ -35,7 +35,7 @@ class hk_params(ctypes.Structure):
         ("rmin", ctypes.c_double), ("n_a", ctypes.c_int32), ("n_s", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("stats_channel", ctypes.c_int32), ("normal_cos_min", ctypes.c_float), ("max_iters", ctypes.c_int32),
         ("cell_scale", ctypes.c_float), ("cell_quantile", ctypes.c_float), ("heavy_cost", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("lanes_light", ctypes.c_int32), ("lanes_heavy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
