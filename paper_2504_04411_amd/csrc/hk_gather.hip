@@ -91,6 +91,7 @@ __device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], 
 }
 
 constexpr int UNROLL = 4;         // candidate loads in flight per lane
+constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
 struct Lds {
     float4 slot[NG][WAVE];        // lane-private S, comp S, Q, comp Q per group
@@ -410,7 +411,14 @@ __global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
     const uint32_t items_h = (n_heavy + KPW_H - 1) / KPW_H;
     const uint32_t n_items = items_h + (n_light + KPW_L - 1) / KPW_L;
     uint64_t pairs = 0, cand = 0;
-    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    // Workgroups are dealt to the 8 XCDs round-robin. Chunk k of XCD_CHUNK consecutive items (a
+    // compact patch along the Morton order) goes to XCD k mod 8, and an XCD walks its chunks in
+    // order, so each XCD's L2 holds the photons of a few patches instead of the whole scene. The
+    // grid is a multiple of 8 * XCD_CHUNK, which makes the map a bijection; items beyond the first
+    // grid are taken in a plain stride loop.
+    const uint32_t b = blockIdx.x, x = b & 7u, w = b >> 3;
+    const uint32_t first = ((w / XCD_CHUNK) * 8u + x) * XCD_CHUNK + (w % XCD_CHUNK);
+    for (uint32_t item = first; item < n_items; item += gridDim.x) {
         if (item < items_h) {
             const uint32_t hi = item * KPW_H + (uint32_t)(lane / GH);
             const bool act = hi < n_heavy;
@@ -456,7 +464,8 @@ void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)
     if (a.H <= 0) return;
     const int gl = (a.lanes_light == 4 || a.lanes_light == 8) ? a.lanes_light : 16;
     const int gh = (a.lanes_heavy == 16) ? 16 : 64;
-    const int grid = (int)cdiv(a.H, WAVE / gl);
+    const int64_t per = 8 * (int64_t)XCD_CHUNK;
+    const int grid = (int)(cdiv(cdiv(a.H, WAVE / gl), per) * per);
     if (nrm && vcm)
         launch_lanes<true, true>(a, gl, gh, grid, s);
     else if (nrm)
