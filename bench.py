@@ -37,6 +37,24 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
+def profiled_traffic():
+    """HBM bytes per launch of the gather kernel from the committed rocprofv3 summary, or None when
+    the kernel sources changed since the counters were taken (their hash is recorded there)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "gather_update_box.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r'^(\{"kernel": "gather_update_kernel".*\})$', open(path).read(), flags=re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for f in ["hk_gather.hip", "hk_internal.h", "hk_kernels.h", "hk_fquant.h"]:
+        h.update(open(os.path.join(ROOT, "paper_2504_04411_amd", "csrc", f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec["source_sha256_16"] else None
+
+
 def _gen(args):
     seed, it, J = args
     from workloads import generators as G
@@ -136,7 +154,7 @@ def main():
     ops = OPS_PER_QUERY * H * K + OPS_PER_PAIR * stats["pairs"]
     achieved = ops / gather_s / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": profiled_traffic(),
             "kernel": "gather_update_kernel<true,false,8,64>", "avg_launch_ms": round(launch_ms, 4),
             "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
     out = {
