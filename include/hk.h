@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define HK_VERSION 100
+#define HK_VERSION 110
 
 /* status codes */
 #define HK_OK 0
@@ -57,6 +57,7 @@ extern "C" {
 #define HK_STATS_RGB 1
 
 typedef struct hk_ctx hk_ctx;
+typedef struct hk_graph hk_graph;
 
 /* Parameters of the estimator (Sec. 5.1 Eq. radiusupdate, Sec. 6 settings). */
 typedef struct hk_params {
@@ -99,32 +100,73 @@ int hk_default_params(double r1, hk_params *p);
 int hk_create(const hk_params *p, hk_ctx **out);
 int hk_destroy(hk_ctx *ctx);
 
-/* Bytes of the per-set state for n_kernels hit points (the caller allocates it on the device). */
+/* The context's parameters, with the defaults filled in and any tuning applied. */
+int hk_get_params(hk_ctx *ctx, hk_params *out);
+
+/* Changes the performance parameters (cell_scale, heavy_cost, lanes_light, lanes_heavy; 0 selects
+ * the default; validated as in hk_create). They change the order of summation, not the estimator:
+ * results agree with any other setting to rounding. Applies to later hk_iterate calls and graphs. */
+int hk_set_tuning(hk_ctx *ctx, float cell_scale, int heavy_cost, int lanes_light, int lanes_heavy);
+
+/* Bytes of the per-set state for n_kernels hit points, 1 <= n_kernels <= 2^26 - 1 (the caller
+ * allocates it on the device). */
 int hk_state_bytes(hk_ctx *ctx, int64_t n_kernels, size_t *out);
 
-/* Bytes of the workspace shared by all sets of one hk_iterate call, for at most max_photons stored
- * light vertices per set and max_kernels kernels per set. */
+/* Bytes of the workspace of one hk_iterate call over n_sets sets with n_photons[s] stored light
+ * vertices and n_kernels[s] kernels (host arrays). The result also covers any subset of the sets,
+ * so one workspace serves every call whose sets are a subset of these, with at most as many
+ * photons each. */
+int hk_workspace_bytes_batch(hk_ctx *ctx, int n_sets, const int64_t *n_photons, const int64_t *n_kernels,
+                             size_t *out);
+
+/* hk_workspace_bytes_batch for one set. */
 int hk_workspace_bytes(hk_ctx *ctx, int64_t max_photons, int64_t max_kernels, size_t *out);
 
 /* Initialises set `set_id` (0..255): copies the n hit points into `state` (device, state_bytes(n)),
  * orders them along a Morton curve, computes tangent frames and clears all statistics (t = 0,
- * sums 0, estimate 0, r = r_init or r1). Inputs (device): pos[3]; nrm[3] or NULL (+z);
- * r_init or NULL; VCM only: cam_beta[3] camera throughput, cam_mis[3] partials dVCM, dVC, dVM.
- * `workspace` (device, at least hk_workspace_bytes(ctx, 0, n) bytes, given in workspace_bytes) is
- * scratch for the ordering. Resets the set's iteration count. */
-int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *const pos[3], const float *const nrm[3],
-                   const float *r_init, const float *const cam_beta[3], const float *const cam_mis[3],
-                   void *state, void *workspace, size_t workspace_bytes, hipStream_t stream);
+ * sums 0, estimate 0, r = r_init or r1). The set's radius scale: r1 (initial radius; <= 0 takes the
+ * context's) and rmin (lower-bound scale of Eq. radiusupdate, in [0, r1]; < 0 keeps the context's
+ * ratio rmin / r1), so sets of different scales can share a context and a batch. Inputs (device):
+ * pos[3]; nrm[3] or NULL (+z); r_init or NULL; VCM only: cam_beta[3] camera throughput, cam_mis[3]
+ * partials dVCM, dVC, dVM. `workspace` (device, at least hk_workspace_bytes(ctx, 0, n) bytes, given
+ * in workspace_bytes) is scratch for the ordering. Resets the set's iteration count. */
+int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, const float *const pos[3],
+                   const float *const nrm[3], const float *r_init, const float *const cam_beta[3],
+                   const float *const cam_mis[3], void *state, void *workspace, size_t workspace_bytes,
+                   hipStream_t stream);
 
-/* Runs one iteration (steps 1-6 above) for each of the n_sets sets; ph[s] holds set s's light
- * vertices and state[s] its state, set_ids[s] its id. Sets run one after the other on `stream`.
- * `workspace` (device, workspace_bytes long) must hold hk_workspace_bytes(ctx, n_stored, H) for
- * every set (HK_E_SMALL_BUFFER otherwise); a set holds at most 2^27 - 1 stored light vertices per
- * iteration (HK_E_UNSUPPORTED). Arguments of all sets are checked before any work is
- * enqueued. Non-finite photon values are not rejected: a NaN position never lands in a disk, a NaN
- * flux makes that kernel's F NaN, which keeps the radius (IEEE comparison). */
+/* Runs one iteration (steps 1-6 above) for each of the n_sets (1..256, distinct) sets; ph[s] holds
+ * set s's light vertices, state[s] its state, set_ids[s] its id. Each set's grid is built by its own
+ * launches; the gather, test and update of up to 64 sets (2^28 - 1 stored light vertices in total)
+ * run as ONE launch over a work list spanning those sets, so many small, uneven sets fill the GPU
+ * together. Sets with and without the normal test go to separate launches. `workspace` (device,
+ * workspace_bytes long) must hold hk_workspace_bytes_batch over the sets (HK_E_SMALL_BUFFER
+ * otherwise); a set holds at most 2^27 - 1 stored light vertices per iteration (HK_E_UNSUPPORTED).
+ * Arguments of all sets are checked before any work is enqueued. Non-finite photon values are not
+ * rejected: a NaN position never lands in a disk, a NaN flux makes that kernel's F NaN, which keeps
+ * the radius (IEEE comparison). */
 int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Captures the launches of one hk_iterate call (same arguments) into a HIP graph, *out. Nothing runs
+ * at capture and no set advances. Each hk_graph_launch then runs one iteration of those sets on
+ * `stream` (the iteration index, J and the radius bounds come from the device-resident state). The
+ * graph reads the photon arrays given here: refill them before each launch; J_emitted and n_stored
+ * stay those of the capture. hk_graph_launch fails with HK_E_BAD_STATE if a set was re-initialised
+ * since, reached max_iters, or ran with another J in between (capture again). */
+int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                    void *workspace, size_t workspace_bytes, hk_graph **out);
+int hk_graph_launch(hk_graph *g, hipStream_t stream);
+int hk_graph_destroy(hk_graph *g);
+
+/* Times one iteration of the given sets for each of 27 settings (cell_scale 0.7 / 1 / 1.4 x
+ * lanes_light 4 / 8 / 16 x heavy_cost 1024 / 4096 / 16384) and keeps the fastest in the context
+ * (copied to *chosen when non-NULL). Each trial runs on scratch[s] (device, hk_state_bytes of the
+ * set, distinct from state[s]) after copying state[s] into it, so the states and the sets'
+ * iteration counts are left unchanged. Synchronises `stream`. */
+int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                void *const *scratch, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                hk_params *chosen);
 
 /* Radiance estimate L = f_r tau / N per channel (f_r = 1/pi), in the caller's original kernel order.
  * out_rgb[3]: device arrays of n floats. */
@@ -139,12 +181,12 @@ int hk_read_debug(hk_ctx *ctx, int set_id, const void *state, uint32_t *count, d
                   uint8_t *decision, uint32_t *t, hipStream_t stream);
 
 /* Retained group sums in float64 (device, n x 12 each, row-major, original order): S and Q as the
- * compensated pairs value - compensation, and the estimate tau (n x 3). */
+ * compensated float32 pairs (value + collected rounding errors), and the estimate tau (n x 3). */
 int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *S, double *Q, double *tau,
                  hipStream_t stream);
 
-/* Running totals of the set since hk_set_kernels, written to out (device, 4 x uint64): [0] gather
- * launches, [1] in-disk (kernel, photon) pairs, [2] kernel x photon candidate tests, [3] grid cells
+/* Running totals of the set since hk_set_kernels, written to out (device, 4 x uint64): [0]
+ * iterations, [1] in-disk (kernel, photon) pairs, [2] kernel x photon candidate tests, [3] grid cells
  * of the last iteration. */
 int hk_read_stats(hk_ctx *ctx, int set_id, const void *state, uint64_t *out, hipStream_t stream);
 
@@ -152,10 +194,10 @@ int hk_read_stats(hk_ctx *ctx, int set_id, const void *state, uint64_t *out, hip
  * device evaluates for the critical value (Sec. 3.2.2). Returns NaN for invalid arguments. */
 double hk_f_quantile(double d1, double d2, double alpha);
 
-/* Timing of the last hk_iterate calls when enabled (hipEvents on the caller's stream):
- * hk_profile_enable(ctx, 1) starts recording, hk_profile_read(ctx, out, n) synchronises on the last
- * event and writes up to n phase totals in milliseconds since enabling: [0] grid build,
- * [1] critical values, [2] gather + test + update, [3] launches of [2] counted. */
+/* Timing of the hk_iterate calls since enabling (hipEvents on the caller's stream; graphs are not
+ * timed): hk_profile_enable(ctx, 1) starts recording, hk_profile_read(ctx, out, n) synchronises on
+ * the last event and writes up to n phase totals in milliseconds: [0] grid builds, [1] critical
+ * values, [2] work list + gather + test + update, [3] gather launches counted. */
 int hk_profile_enable(hk_ctx *ctx, int on);
 int hk_profile_read(hk_ctx *ctx, double *out, int n);
 

@@ -37,15 +37,18 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 constexpr int MAX_SETS = 256;
+constexpr int64_t MAX_KERNELS = ((int64_t)1 << Q_BITS) - 1;       // per set
+constexpr int64_t MAX_STORED = ((int64_t)1 << 27) - 1;            // per set and iteration
+constexpr int64_t MAX_BATCH_PHOTONS = ((int64_t)1 << 28) - 1;     // per gather launch (32-bit offsets)
 
 struct SetInfo {
     bool init = false;
+    uint64_t gen = 0;          // bumped by every hk_set_kernels (a graph records the generation)
     int64_t H = 0;
     int iter = 0;              // completed iterations
     bool has_nrm = false;
     bool J_const = true;       // every J so far equal -> table entries t < iter stay valid
     uint64_t J_first = 0;
-    int fc_valid_upto = 0;     // fctab[1..fc_valid_upto] computed for the current J history
 };
 
 struct ProfEv {
@@ -58,9 +61,19 @@ struct hk_ctx {
     hk_params p;
     int device = 0;
     SetInfo sets[MAX_SETS];
+    uint64_t gen = 0;
     bool prof = false;
     std::vector<ProfEv> ev_used, ev_free;
-    double prof_ms[4] = {0, 0, 0, 0};
+    hipStream_t cap = nullptr;     // stream used for graph capture (created on first use)
+};
+
+struct hk_graph {
+    hk_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> ids;
+    std::vector<uint64_t> gen, J;
+    std::vector<char> all;     // critical-value table recomputed in full (J varied before capture)
 };
 
 static bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
@@ -92,6 +105,27 @@ extern "C" int hk_default_params(double r1, hk_params *p)
     return HK_OK;
 }
 
+static int check_tunables(const hk_params *p)
+{
+    if (!(p->cell_scale >= 0.0f && isfinite(p->cell_scale))) return fail(HK_E_INVALID_ARG, "bad cell_scale");
+    if (!(p->cell_quantile >= 0.0f && p->cell_quantile <= 1.0f)) return fail(HK_E_INVALID_ARG, "bad cell_quantile");
+    if (p->heavy_cost < 0) return fail(HK_E_INVALID_ARG, "heavy_cost must be >= 0");
+    if (p->lanes_light != 0 && p->lanes_light != 4 && p->lanes_light != 8 && p->lanes_light != 16)
+        return fail(HK_E_INVALID_ARG, "lanes_light must be 4, 8 or 16");
+    if (p->lanes_heavy != 0 && p->lanes_heavy != 16 && p->lanes_heavy != 64)
+        return fail(HK_E_INVALID_ARG, "lanes_heavy must be 16 or 64");
+    return HK_OK;
+}
+
+static void fill_tunable_defaults(hk_params *p)
+{
+    if (p->cell_scale == 0.0f) p->cell_scale = 1.0f;
+    if (p->cell_quantile == 0.0f) p->cell_quantile = 0.5f;
+    if (p->heavy_cost <= 0) p->heavy_cost = 4096;
+    if (p->lanes_light == 0) p->lanes_light = 8;
+    if (p->lanes_heavy == 0) p->lanes_heavy = 64;
+}
+
 extern "C" int hk_create(const hk_params *p, hk_ctx **out)
 {
     if (!p || !out) return fail(HK_E_INVALID_ARG, "hk_create: NULL argument");
@@ -108,20 +142,12 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
     if (!(p->normal_cos_min >= -1.0f && p->normal_cos_min <= 1.0f))
         return fail(HK_E_INVALID_ARG, "normal_cos_min must be in [-1, 1]");
     if (p->max_iters < 1 || p->max_iters > 65536) return fail(HK_E_INVALID_ARG, "max_iters must be in [1, 65536]");
-    if (!(p->cell_scale >= 0.0f && isfinite(p->cell_scale))) return fail(HK_E_INVALID_ARG, "bad cell_scale");
-    if (!(p->cell_quantile >= 0.0f && p->cell_quantile <= 1.0f)) return fail(HK_E_INVALID_ARG, "bad cell_quantile");
-    if (p->lanes_light != 0 && p->lanes_light != 4 && p->lanes_light != 8 && p->lanes_light != 16)
-        return fail(HK_E_INVALID_ARG, "lanes_light must be 4, 8 or 16");
-    if (p->lanes_heavy != 0 && p->lanes_heavy != 16 && p->lanes_heavy != 64)
-        return fail(HK_E_INVALID_ARG, "lanes_heavy must be 16 or 64");
+    int rc = check_tunables(p);
+    if (rc) return rc;
     hk_ctx *c = new (std::nothrow) hk_ctx();
     if (!c) return fail(HK_E_INVALID_ARG, "out of host memory");
     c->p = *p;
-    if (c->p.cell_scale == 0.0f) c->p.cell_scale = 1.0f;
-    if (c->p.cell_quantile == 0.0f) c->p.cell_quantile = 0.5f;
-    if (c->p.heavy_cost <= 0) c->p.heavy_cost = 4096;
-    if (c->p.lanes_light == 0) c->p.lanes_light = 8;
-    if (c->p.lanes_heavy == 0) c->p.lanes_heavy = 64;
+    fill_tunable_defaults(&c->p);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(HK_E_HIP, "hipGetDevice failed");
@@ -136,39 +162,76 @@ extern "C" int hk_destroy(hk_ctx *ctx)
     for (auto &v : {&ctx->ev_used, &ctx->ev_free})
         for (auto &pe : *v)
             for (auto e : pe.e) (void)hipEventDestroy(e);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
     return HK_OK;
 }
 
-static Layout layout_of(const hk_ctx *ctx, int64_t H) { return make_layout(H, ctx->p.max_iters, false); }
+extern "C" int hk_get_params(hk_ctx *ctx, hk_params *out)
+{
+    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_get_params: NULL argument");
+    *out = ctx->p;
+    return HK_OK;
+}
+
+extern "C" int hk_set_tuning(hk_ctx *ctx, float cell_scale, int heavy_cost, int lanes_light, int lanes_heavy)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_set_tuning: NULL context");
+    hk_params q = ctx->p;
+    q.cell_scale = cell_scale;
+    q.heavy_cost = heavy_cost;
+    q.lanes_light = lanes_light;
+    q.lanes_heavy = lanes_heavy;
+    int rc = check_tunables(&q);
+    if (rc) return rc;
+    fill_tunable_defaults(&q);
+    ctx->p = q;
+    return HK_OK;
+}
+
+static Layout layout_of(const hk_ctx *ctx, int64_t H) { return make_layout(H, ctx->p.max_iters); }
 
 extern "C" int hk_state_bytes(hk_ctx *ctx, int64_t n_kernels, size_t *out)
 {
     if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_state_bytes: NULL argument");
-    if (n_kernels < 1 || n_kernels > (int64_t)INT32_MAX - 64) return fail(HK_E_INVALID_ARG, "n_kernels out of range");
+    if (n_kernels < 1 || n_kernels > MAX_KERNELS)
+        return fail(HK_E_INVALID_ARG, "n_kernels must be in [1, %lld]", (long long)MAX_KERNELS);
     *out = layout_of(ctx, n_kernels).total;
+    return HK_OK;
+}
+
+extern "C" int hk_workspace_bytes_batch(hk_ctx *ctx, int n_sets, const int64_t *n_photons, const int64_t *n_kernels,
+                                        size_t *out)
+{
+    if (!ctx || !out || !n_photons || !n_kernels || n_sets < 1)
+        return fail(HK_E_INVALID_ARG, "hk_workspace_bytes_batch: bad argument");
+    for (int s = 0; s < n_sets; ++s)
+        if (n_photons[s] < 0 || n_photons[s] > MAX_STORED || n_kernels[s] < 0 || n_kernels[s] > MAX_KERNELS)
+            return fail(HK_E_INVALID_ARG, "sizes of set %d out of range", s);
+    *out = make_ws_layout(n_sets, n_photons, n_kernels).total;
     return HK_OK;
 }
 
 extern "C" int hk_workspace_bytes(hk_ctx *ctx, int64_t max_photons, int64_t max_kernels, size_t *out)
 {
-    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_workspace_bytes: NULL argument");
-    if (max_photons < 0 || max_photons > (int64_t)UINT32_MAX - 1024 || max_kernels < 0 ||
-        max_kernels > (int64_t)INT32_MAX - 64)
-        return fail(HK_E_INVALID_ARG, "sizes out of range");
-    *out = make_ws_layout(max_photons, max_kernels).total;
-    return HK_OK;
+    return hk_workspace_bytes_batch(ctx, 1, &max_photons, &max_kernels, out);
 }
 
 static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
-extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *const pos[3], const float *const nrm[3],
-                              const float *r_init, const float *const cam_beta[3], const float *const cam_mis[3],
-                              void *state, void *workspace, size_t workspace_bytes, hipStream_t stream)
+extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, const float *const pos[3],
+                              const float *const nrm[3], const float *r_init, const float *const cam_beta[3],
+                              const float *const cam_mis[3], void *state, void *workspace, size_t workspace_bytes,
+                              hipStream_t stream)
 {
     if (!ctx) return fail(HK_E_INVALID_ARG, "hk_set_kernels: NULL context");
+    // per-set radius scale: r1 <= 0 takes the context's, rmin < 0 keeps the context's ratio rmin / r1
+    if (!(r1 > 0.0)) r1 = ctx->p.r1;
+    if (!(rmin >= 0.0)) rmin = ctx->p.rmin * (r1 / (double)ctx->p.r1);
+    if (!finite_pos((float)r1)) return fail(HK_E_INVALID_ARG, "r1 must be finite and > 0");
+    if (!(rmin <= r1 * (1.0 + 1e-7))) return fail(HK_E_INVALID_ARG, "rmin must be in [0, r1]");
     if (set_id < 0 || set_id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set_id out of range");
-    if (n < 1 || n > (int64_t)INT32_MAX - 64) return fail(HK_E_INVALID_ARG, "n out of range");
+    if (n < 1 || n > MAX_KERNELS) return fail(HK_E_INVALID_ARG, "n must be in [1, %lld]", (long long)MAX_KERNELS);
     if (!pos || !pos[0] || !pos[1] || !pos[2]) return fail(HK_E_INVALID_ARG, "pos is NULL");
     if (!state || !aligned(state)) return fail(HK_E_INVALID_ARG, "state must be non-NULL and 256-byte aligned");
     if (!workspace || !aligned(workspace)) return fail(HK_E_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -178,7 +241,8 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *c
     if (vcm && (!cam_beta || !cam_beta[0] || !cam_beta[1] || !cam_beta[2] || !cam_mis || !cam_mis[0] ||
                 !cam_mis[2]))
         return fail(HK_E_INVALID_ARG, "vertex merging needs cam_beta[3] and cam_mis (dVCM, -, dVM)");
-    const WsLayout W = make_ws_layout(0, n);
+    const int64_t zero = 0;
+    const WsLayout W = make_ws_layout(1, &zero, &n);
     if (workspace_bytes < W.total)
         return fail(HK_E_SMALL_BUFFER, "workspace of %zu bytes, %zu needed", workspace_bytes, W.total);
     HIP_TRY(hipSetDevice(ctx->device));
@@ -195,9 +259,8 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *c
     g.src.r_init = r_init;
     g.n = n;
     g.max_iters = ctx->p.max_iters;
-    g.r1 = ctx->p.r1;
+    g.r1 = (float)r1;
     g.vcm = vcm;
-    g.nsq = NSQ;
     g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
     g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
     g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
@@ -205,10 +268,16 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, const float *c
     g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
     g.part = reinterpret_cast<uint32_t *>(w + W.part);
     init_set(g, stream);
+    // lower bounds lb_i = r_min sqrt(i^(alpha - 1)) of Eq. radiusupdate, float64 then one rounding
+    std::vector<float> lb((size_t)ctx->p.max_iters + 2);
+    for (size_t i = 0; i < lb.size(); ++i)
+        lb[i] = (float)(rmin * sqrt(pow((double)(i > 0 ? i : 1), ctx->p.alpha - 1.0)));
+    launch_upload(g.st.lbtab, lb.data(), sizeof(float) * lb.size(), stream);
     HIP_TRY(hipGetLastError());
     SetInfo &S = ctx->sets[set_id];
     S = SetInfo();
     S.init = true;
+    S.gen = ++ctx->gen;
     S.H = n;
     S.has_nrm = has_nrm;
     return HK_OK;
@@ -227,17 +296,26 @@ static ProfEv *prof_slot(hk_ctx *ctx)
     return &ctx->ev_used.back();
 }
 
-extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
-                          void *workspace, size_t workspace_bytes, hipStream_t stream)
+static bool nrm_test_of(const hk_ctx *ctx, int id, const hk_photons &P)
 {
-    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_iterate: NULL context");
-    if (n_sets < 1 || !set_ids || !ph || !state) return fail(HK_E_INVALID_ARG, "hk_iterate: bad set arguments");
+    return ctx->sets[id].has_nrm && P.nrm[0] != nullptr;
+}
+
+// Checks every set of a call before anything is enqueued (a graph's replays are checked again at
+// launch).
+static int validate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                    void *workspace)
+{
+    if (n_sets < 1 || n_sets > MAX_SETS || !set_ids || !ph || !state)
+        return fail(HK_E_INVALID_ARG, "bad set arguments (n_sets in [1, %d], arrays non-NULL)", MAX_SETS);
     if (!workspace || !aligned(workspace)) return fail(HK_E_INVALID_ARG, "workspace must be 256-byte aligned");
     const bool vcm = ctx->p.mode == HK_MODE_VCM;
-    // validate everything before enqueuing anything
+    bool seen[MAX_SETS] = {};
     for (int s = 0; s < n_sets; ++s) {
         const int id = set_ids[s];
         if (id < 0 || id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", id);
+        if (seen[id]) return fail(HK_E_INVALID_ARG, "set id %d appears twice in one call", id);
+        seen[id] = true;
         if (!ctx->sets[id].init) return fail(HK_E_BAD_STATE, "set %d has no kernels (call hk_set_kernels)", id);
         if (ctx->sets[id].iter >= ctx->p.max_iters) return fail(HK_E_BAD_STATE, "set %d reached max_iters", id);
         if (!state[s] || !aligned(state[s])) return fail(HK_E_INVALID_ARG, "state of set %d not aligned", id);
@@ -245,7 +323,7 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
         if (P.J_emitted < 1 || P.n_stored < 0 || (uint64_t)P.n_stored > P.J_emitted)
             return fail(HK_E_INVALID_ARG, "set %d: need 1 <= J_emitted and 0 <= n_stored <= J_emitted", id);
         if (P.J_emitted > (uint64_t)1 << 52) return fail(HK_E_INVALID_ARG, "J_emitted too large");
-        if (P.n_stored >= ((int64_t)1 << 27))
+        if (P.n_stored > MAX_STORED)
             return fail(HK_E_UNSUPPORTED, "set %d: at most 2^27 - 1 stored light vertices per set", id);
         if (P.n_stored > 0) {
             for (int a = 0; a < 3; ++a)
@@ -253,121 +331,334 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
             if (vcm && (!P.mis[0] || !P.mis[2])) return fail(HK_E_INVALID_ARG, "set %d: mis partials needed", id);
             if (ctx->sets[id].has_nrm && !P.nrm[0] && (P.nrm[1] || P.nrm[2]))
                 return fail(HK_E_INVALID_ARG, "set %d: nrm must be all NULL or all set", id);
+            if (nrm_test_of(ctx, id, P) && (!P.nrm[1] || !P.nrm[2]))
+                return fail(HK_E_INVALID_ARG, "set %d: nrm must be all NULL or all set", id);
         }
-        const WsLayout W = make_ws_layout(P.n_stored, ctx->sets[id].H);
+    }
+    return HK_OK;
+}
+
+// Batches of one gather launch: sets of equal normal-test flag, at most MAX_BATCH sets and
+// MAX_BATCH_PHOTONS stored light vertices each, in call order within a flag.
+static std::vector<std::vector<int>> make_batches(const hk_ctx *ctx, int n_sets, const int *set_ids,
+                                                  const hk_photons *ph)
+{
+    std::vector<std::vector<int>> out;
+    for (int flag = 1; flag >= 0; --flag) {
+        std::vector<int> cur;
+        int64_t np = 0;
+        for (int s = 0; s < n_sets; ++s) {
+            if ((int)nrm_test_of(ctx, set_ids[s], ph[s]) != flag) continue;
+            if (!cur.empty() && ((int)cur.size() == MAX_BATCH || np + ph[s].n_stored > MAX_BATCH_PHOTONS)) {
+                out.push_back(cur);
+                cur.clear();
+                np = 0;
+            }
+            cur.push_back(s);
+            np += ph[s].n_stored;
+        }
+        if (!cur.empty()) out.push_back(cur);
+    }
+    return out;
+}
+
+static WsLayout batch_layout(const hk_ctx *ctx, const std::vector<int> &b, const int *set_ids, const hk_photons *ph)
+{
+    int64_t np[MAX_BATCH], nk[MAX_BATCH];
+    for (size_t k = 0; k < b.size(); ++k) {
+        np[k] = ph[b[k]].n_stored;
+        nk[k] = ctx->sets[set_ids[b[k]]].H;
+    }
+    return make_ws_layout((int)b.size(), np, nk);
+}
+
+// Whether the critical-value table must be recomputed in full at the next iteration of set id with
+// J light sub-paths (J differs from an earlier iteration's), else only its new entry.
+static bool fcrit_all(const SetInfo &S, uint64_t J)
+{
+    return !(S.J_const && (S.iter == 0 || J == S.J_first));
+}
+
+static void advance(SetInfo &S, uint64_t J)
+{
+    if (S.iter == 0) S.J_first = J;
+    if (J != S.J_first) S.J_const = false;
+    S.iter += 1;
+}
+
+// Enqueues one iteration of every set (no host bookkeeping: the caller advances the sets).
+static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                   void *workspace, size_t workspace_bytes, hipStream_t stream, bool prof, const char *all_in,
+                   std::vector<char> *all_out)
+{
+    const hk_params &p = ctx->p;
+    const bool vcm = p.mode == HK_MODE_VCM;
+    const auto batches = make_batches(ctx, n_sets, set_ids, ph);
+    for (const auto &b : batches) {
+        const WsLayout W = batch_layout(ctx, b, set_ids, ph);
         if (workspace_bytes < W.total)
             return fail(HK_E_SMALL_BUFFER, "workspace of %zu bytes, %zu needed", workspace_bytes, W.total);
     }
-    HIP_TRY(hipSetDevice(ctx->device));
-    const hk_params &p = ctx->p;
-    for (int s = 0; s < n_sets; ++s) {
-        const int id = set_ids[s];
-        SetInfo &S = ctx->sets[id];
-        const hk_photons &P = ph[s];
-        const Layout L = layout_of(ctx, S.H);
-        const StateView st = make_view(state[s], L);
-        const WsLayout W = make_ws_layout(P.n_stored, S.H);
-        char *w = static_cast<char *>(workspace);
-        const int i = S.iter + 1;
-        if (i == 1) S.J_first = P.J_emitted;
-        if (P.J_emitted != S.J_first) S.J_const = false;
-        ProfEv *pe = ctx->prof ? prof_slot(ctx) : nullptr;
-        if (ctx->prof && !pe) return fail(HK_E_HIP, "hipEventCreate failed");
+    if (all_out) all_out->assign(n_sets, 0);
+    char *w = static_cast<char *>(workspace);
+    for (const auto &b : batches) {
+        const WsLayout W = batch_layout(ctx, b, set_ids, ph);
+        const int nb = (int)b.size();
+        const bool nrm_test = nrm_test_of(ctx, set_ids[b[0]], ph[b[0]]);
+        ProfEv *pe = prof ? prof_slot(ctx) : nullptr;
+        if (prof && !pe) return fail(HK_E_HIP, "hipEventCreate failed");
         if (pe) HIP_TRY(hipEventRecord(pe->e[0], stream));
-
-        launch_plan(st.hdr, st.mprefix, i, (double)P.J_emitted, p.cell_scale, p.cell_quantile, W.max_cells, stream);
-        GridLaunch g{};
-        g.hdr = st.hdr;
-        for (int a = 0; a < 3; ++a) {
-            g.src.pos[a] = P.pos[a];
-            g.src.nrm[a] = S.has_nrm ? P.nrm[a] : nullptr;
-            g.src.flux[a] = P.flux[a];
-            g.src.mis[a] = vcm ? P.mis[a] : nullptr;
+        uint32_t *ws_cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
+        float4 *ws_pay = reinterpret_cast<float4 *>(w + W.pay);
+        // 1. per set: advance the iteration on the device, choose the cell size, sort the photons
+        for (int k = 0; k < nb; ++k) {
+            const int s = b[k];
+            const SetInfo &S = ctx->sets[set_ids[s]];
+            const hk_photons &P = ph[s];
+            const StateView st = make_view(state[s], layout_of(ctx, S.H));
+            launch_plan(st.hdr, st.mprefix, (double)P.J_emitted, p.cell_scale, p.cell_quantile, W.max_cells[k],
+                        stream);
+            GridLaunch g{};
+            g.hdr = st.hdr;
+            for (int a = 0; a < 3; ++a) {
+                g.src.pos[a] = P.pos[a];
+                g.src.nrm[a] = nrm_test ? P.nrm[a] : nullptr;
+                g.src.flux[a] = P.flux[a];
+                g.src.mis[a] = vcm ? P.mis[a] : nullptr;
+            }
+            g.n = P.n_stored;
+            g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
+            g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
+            g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
+            g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
+            g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
+            g.part = reinterpret_cast<uint32_t *>(w + W.part);
+            g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
+            g.cstart = ws_cstart + W.cell_base[k];
+            g.pay = ws_pay + W.pay_off[k];
+            g.pstride = W.n_total;
+            g.ncells_bound = W.max_cells[k];
+            build_grid(g, stream);
         }
-        const bool nrm_test = S.has_nrm && P.nrm[0] != nullptr;
-        if (!nrm_test)
-            for (int a = 0; a < 3; ++a) g.src.nrm[a] = nullptr;
-        g.n = P.n_stored;
-        g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
-        g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
-        g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
-        g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
-        g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
-        g.part = reinterpret_cast<uint32_t *>(w + W.part);
-        g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
-        g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
-        g.pay = reinterpret_cast<float4 *>(w + W.pay);
-        g.pstride = P.n_stored;
-        g.ncells_bound = W.max_cells;
-        build_grid(g, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
-
-        // critical values for t = 1..i; with a constant J only the new entry t = i changes
-        const int t_lo = (S.J_const && S.fc_valid_upto == i - 1) ? i : 1;
-        launch_fcrit(st.fctab, st.mprefix, i, t_lo, i, p.alpha_f, stream);
-        S.fc_valid_upto = S.J_const ? i : 0;
-        if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
-
-        ListLaunch wl{};
-        wl.H = S.H;
-        wl.hdr = st.hdr;
-        wl.cstart = g.cstart;
-        for (int k = 0; k < 3; ++k) wl.kp[k] = st.pos[k];
-        wl.r = st.r;
-        wl.heavy_cost = (uint32_t)p.heavy_cost;
-        wl.flag = reinterpret_cast<uint32_t *>(w + W.flag);
-        wl.offs = reinterpret_cast<uint32_t *>(w + W.offs);
-        wl.part2 = reinterpret_cast<uint32_t *>(w + W.part2);
-        wl.heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
-        wl.light = reinterpret_cast<uint32_t *>(w + W.light);
-        wl.counts = reinterpret_cast<uint32_t *>(w + W.counts);
-        build_work_list(wl, stream);
-
-        GatherArgs a{};
-        a.H = S.H;
-        a.hdr = st.hdr;
-        a.cstart = g.cstart;
-        a.payA = g.pay;
-        a.payB = g.pay + g.pstride;
-        a.payC = g.pay + 2 * g.pstride;
-        a.npay = (uint32_t)P.n_stored;
-        a.heavy = wl.heavy;
-        a.light = wl.light;
-        a.counts = wl.counts;
-        a.lanes_light = p.lanes_light;
-        a.lanes_heavy = p.lanes_heavy;
-        for (int k = 0; k < 3; ++k) {
-            a.kp[k] = st.pos[k];
-            a.kn[k] = st.nrm[k];
-            a.ku[k] = st.u[k];
-            a.kv[k] = st.v[k];
-            a.cb[k] = st.cb[k];
+        // 2. per set: critical values for the kept-iteration counts this iteration can reach
+        for (int k = 0; k < nb; ++k) {
+            const int s = b[k];
+            const SetInfo &S = ctx->sets[set_ids[s]];
+            const StateView st = make_view(state[s], layout_of(ctx, S.H));
+            const bool all = all_in ? all_in[s] != 0 : fcrit_all(S, ph[s].J_emitted);
+            if (all_out) (*all_out)[s] = all ? 1 : 0;
+            launch_fcrit(st.hdr, st.fctab, st.mprefix, p.max_iters, all, p.alpha_f, stream);
         }
-        a.r = st.r;
-        a.t = st.t;
-        a.nseen = st.nseen;
-        a.cnt = st.cnt;
-        a.dec = st.dec;
-        a.sq0 = st.sq[0];
-        a.tau0 = st.tau[0];
-        a.astride = (uint32_t)(align256(sizeof(float) * (size_t)S.H) / sizeof(float));
-        a.F = st.F;
-        a.Fc = st.Fc;
-        a.cdvcm = st.cdvcm;
-        a.cdvm = st.cdvm;
-        a.fctab = st.fctab;
-        a.mprefix = st.mprefix;
-        a.iter = i;
-        a.Jf = (float)P.J_emitted;
-        a.lb = (float)(p.rmin * sqrt(pow((double)(i + 1), p.alpha - 1.0)));
+        if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
+        // 3. one work list over the batch, the set table, one gather / test / update launch, then the
+        //    radius histograms and pair counts of the batch's sets
+        uint32_t *flag = reinterpret_cast<uint32_t *>(w + W.flag);
+        uint32_t *offs = reinterpret_cast<uint32_t *>(w + W.offs);
+        uint32_t *ids = reinterpret_cast<uint32_t *>(w + W.ids);
+        SetDesc desc[MAX_BATCH];
+        for (int k = 0; k < nb; ++k) {
+            const int s = b[k];
+            const SetInfo &S = ctx->sets[set_ids[s]];
+            const Layout L = layout_of(ctx, S.H);
+            const StateView st = make_view(state[s], L);
+            ListLaunch l{};
+            l.H = S.H;
+            l.hdr = st.hdr;
+            l.cstart = ws_cstart + W.cell_base[k];
+            for (int a = 0; a < 3; ++a) l.kp[a] = st.pos[a];
+            l.r = st.r;
+            l.heavy_cost = (uint32_t)p.heavy_cost;
+            l.set_slot = (uint32_t)k;
+            l.flag = flag + W.q_off[k];
+            l.offs = offs + W.q_off[k];
+            l.ids = ids + W.q_off[k];
+            launch_cost(l, stream);
+            SetDesc &d = desc[k];
+            memset(&d, 0, sizeof d);
+            d.state = static_cast<char *>(state[s]);
+            d.arr = L.arr;
+            d.stride = L.stride;
+            d.H = (uint32_t)S.H;
+            d.pay_off = W.pay_off[k];
+            d.cell_base = W.cell_base[k];
+            d.max_iters = (uint32_t)p.max_iters;
+            d.mprefix = L.mprefix;
+            d.fctab = L.fctab;
+            d.lbtab = L.lbtab;
+            d.hdr = L.hdr;
+        }
+        uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
+        uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
+        uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
+        launch_split(flag, offs, ids, W.h_total, reinterpret_cast<uint32_t *>(w + W.part2), heavy, light, counts,
+                     stream);
+        SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
+        launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
+        BatchArgs a{};
+        a.desc = table;
+        a.pay = ws_pay;
+        a.pstride = (uint32_t)W.n_total;
+        a.cstart = ws_cstart;
+        a.heavy = heavy;
+        a.light = light;
+        a.counts = counts;
         a.k = p.k;
         a.cos_min = p.normal_cos_min;
-        a.r1 = p.r1;
-        launch_gather(a, nrm_test, vcm, stream);
+        a.lanes_light = p.lanes_light;
+        a.lanes_heavy = p.lanes_heavy;
+        launch_gather(a, W.h_total, nrm_test, vcm, stream);
+        launch_tally(table, ids, W.h_total, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[3], stream));
         HIP_TRY(hipGetLastError());
-        S.iter = i;
     }
+    return HK_OK;
+}
+
+extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                          void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_iterate: NULL context");
+    int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    rc = enqueue(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, stream, ctx->prof, nullptr, nullptr);
+    if (rc) return rc;
+    for (int s = 0; s < n_sets; ++s) advance(ctx->sets[set_ids[s]], ph[s].J_emitted);
+    return HK_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// graphs: one iteration of a fixed list of sets captured once, replayed per iteration
+// ------------------------------------------------------------------------------------------------
+
+extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                               void *workspace, size_t workspace_bytes, hk_graph **out)
+{
+    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_graph_create: NULL argument");
+    *out = nullptr;
+    int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    hk_graph *g = new (std::nothrow) hk_graph();
+    if (!g) return fail(HK_E_INVALID_ARG, "out of host memory");
+    g->ctx = ctx;
+    HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    rc = enqueue(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, ctx->cap, false, nullptr, &g->all);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return rc ? rc : fail(HK_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    g->graph = graph;
+    const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return fail(HK_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    for (int s = 0; s < n_sets; ++s) {
+        g->ids.push_back(set_ids[s]);
+        g->gen.push_back(ctx->sets[set_ids[s]].gen);
+        g->J.push_back(ph[s].J_emitted);
+    }
+    *out = g;
+    return HK_OK;
+}
+
+extern "C" int hk_graph_launch(hk_graph *g, hipStream_t stream)
+{
+    if (!g || !g->ctx) return fail(HK_E_INVALID_ARG, "hk_graph_launch: NULL graph");
+    hk_ctx *ctx = g->ctx;
+    for (size_t s = 0; s < g->ids.size(); ++s) {
+        const SetInfo &S = ctx->sets[g->ids[s]];
+        if (!S.init || S.gen != g->gen[s])
+            return fail(HK_E_BAD_STATE, "set %d was re-initialised after the graph was captured", g->ids[s]);
+        if (S.iter >= ctx->p.max_iters) return fail(HK_E_BAD_STATE, "set %d reached max_iters", g->ids[s]);
+        if (!g->all[s] && fcrit_all(S, g->J[s]))
+            return fail(HK_E_BAD_STATE, "set %d ran with another J since the capture; capture again", g->ids[s]);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipGraphLaunch(g->exec, stream));
+    for (size_t s = 0; s < g->ids.size(); ++s) advance(ctx->sets[g->ids[s]], g->J[s]);
+    return HK_OK;
+}
+
+extern "C" int hk_graph_destroy(hk_graph *g)
+{
+    if (!g) return fail(HK_E_INVALID_ARG, "hk_graph_destroy: NULL graph");
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HK_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// autotuning: time one iteration per candidate on copies of the states, keep the fastest
+// ------------------------------------------------------------------------------------------------
+
+extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                           void *const *scratch, void *workspace, size_t workspace_bytes, hipStream_t stream,
+                           hk_params *chosen)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_autotune: NULL context");
+    int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
+    if (rc) return rc;
+    if (!scratch) return fail(HK_E_INVALID_ARG, "scratch is NULL");
+    for (int s = 0; s < n_sets; ++s)
+        if (!scratch[s] || !aligned(scratch[s]) || scratch[s] == state[s])
+            return fail(HK_E_INVALID_ARG, "scratch of set %d must be a separate 256-byte aligned buffer", set_ids[s]);
+    HIP_TRY(hipSetDevice(ctx->device));
+    static const float cells[] = {0.7f, 1.0f, 1.4f};
+    static const int lanes[] = {4, 8, 16};
+    static const int heavies[] = {1024, 4096, 16384};
+    const hk_params saved = ctx->p;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    hk_params best = saved;
+    rc = HK_OK;
+    auto copy_states = [&]() -> int {
+        for (int s = 0; s < n_sets; ++s) {
+            const size_t bytes = layout_of(ctx, ctx->sets[set_ids[s]].H).total;
+            HIP_TRY(hipMemcpyAsync(scratch[s], state[s], bytes, hipMemcpyDeviceToDevice, stream));
+        }
+        return HK_OK;
+    };
+    // the first trial (the current settings) also warms up code and caches; it is timed again last
+    for (int trial = -1; trial < 27 && rc == HK_OK; ++trial) {
+        hk_params q = saved;
+        if (trial >= 0) {
+            q.cell_scale = cells[trial / 9];
+            q.lanes_light = lanes[(trial / 3) % 3];
+            q.heavy_cost = heavies[trial % 3];
+        }
+        ctx->p = q;
+        rc = copy_states();
+        if (rc) break;
+        hipError_t e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) {
+            rc = enqueue(ctx, n_sets, set_ids, ph, scratch, workspace, workspace_bytes, stream, false, nullptr, nullptr);
+            e = hipEventRecord(e1, stream);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = fail(HK_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+        if (rc == HK_OK && trial >= 0 && ms < best_ms) {
+            best_ms = ms;
+            best = q;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->p = rc == HK_OK ? best : saved;
+    if (rc) return rc;
+    if (chosen) *chosen = ctx->p;
     return HK_OK;
 }
 
@@ -382,9 +673,11 @@ __global__ void read_radiance_kernel(StateView st, int64_t n, float scale, float
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const uint32_t j = st.orig[s];
-    oR[j] = (st.tau[0][s] - st.tau[1][s]) * scale;
-    oG[j] = (st.tau[2][s] - st.tau[3][s]) * scale;
-    oB[j] = (st.tau[4][s] - st.tau[5][s]) * scale;
+    const float *tau = st.tau0 + s;
+    const size_t a = st.astride;
+    oR[j] = (tau[0] + tau[a]) * scale;
+    oG[j] = (tau[2 * a] + tau[3 * a]) * scale;
+    oB[j] = (tau[4 * a] + tau[5 * a]) * scale;
 }
 
 __global__ void read_radii_kernel(StateView st, int64_t n, float *out)
@@ -411,12 +704,14 @@ __global__ void read_sums_kernel(StateView st, int64_t n, double *S, double *Q, 
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const uint32_t j = st.orig[s];
+    const size_t a = st.astride;
+    const float *sq = st.sq0 + s, *tv = st.tau0 + s;
     for (int g = 0; g < NG; ++g) {
-        if (S) S[(int64_t)j * NG + g] = (double)st.sq[4 * g][s] - (double)st.sq[4 * g + 1][s];
-        if (Q) Q[(int64_t)j * NG + g] = (double)st.sq[4 * g + 2][s] - (double)st.sq[4 * g + 3][s];
+        if (S) S[(int64_t)j * NG + g] = (double)sq[(4 * g) * a] + (double)sq[(4 * g + 1) * a];
+        if (Q) Q[(int64_t)j * NG + g] = (double)sq[(4 * g + 2) * a] + (double)sq[(4 * g + 3) * a];
     }
     if (tau)
-        for (int c = 0; c < 3; ++c) tau[(int64_t)j * 3 + c] = (double)st.tau[2 * c][s] - (double)st.tau[2 * c + 1][s];
+        for (int c = 0; c < 3; ++c) tau[(int64_t)j * 3 + c] = (double)tv[(2 * c) * a] + (double)tv[(2 * c + 1) * a];
 }
 
 }  // namespace
@@ -515,7 +810,6 @@ extern "C" int hk_profile_enable(hk_ctx *ctx, int on)
     ctx->prof = on != 0;
     for (auto &pe : ctx->ev_used) ctx->ev_free.push_back(pe);
     ctx->ev_used.clear();
-    for (double &x : ctx->prof_ms) x = 0.0;
     return HK_OK;
 }
 
@@ -524,7 +818,7 @@ extern "C" int hk_profile_read(hk_ctx *ctx, double *out, int n)
     if (!ctx || !out || n < 0) return fail(HK_E_INVALID_ARG, "bad arguments");
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->ev_used.empty()) HIP_TRY(hipEventSynchronize(ctx->ev_used.back().e[3]));
-    double acc[4] = {0, 0, 0, 0};
+    double acc[4] = {0, 0, 0, 0};   // grid, critical values, list + gather, batches
     for (auto &pe : ctx->ev_used) {
         float ms;
         for (int k = 0; k < 3; ++k) {

@@ -1,4 +1,5 @@
-// Fused gather, grouped compensated sums, ANOVA F-test and radius / estimate update for one set.
+// Fused gather, grouped compensated sums, ANOVA F-test and radius / estimate update for a batch of
+// hit-point sets.
 //
 // Work decomposition: G lanes of a wavefront serve one kernel (hit point). The kernel's grid
 // stencil (cells overlapping the box [x - r, x + r], grown by a rounding margin) is a list of rows
@@ -12,14 +13,18 @@
 // lanes accumulate them together, so the accumulation runs with every lane busy instead of only the
 // third of lanes whose candidate fell inside the disk.
 //
-// Light kernels use G = 16 (four kernels per wave); kernels whose stencil holds more than
-// `heavy_cost` photons get a wave of their own (G = 64) and are listed first, so the longest work
-// starts first. The list is rebuilt every iteration from the grid (cost = photons in the stencil).
+// Light kernels share a wave (8 lanes each by default); kernels whose stencil holds more than
+// `heavy_cost` photons get a whole wave and are listed first, so the longest work starts first. The
+// list is rebuilt every iteration from the grid (cost = photons in the stencil) and spans every set
+// of the batch: one launch serves many hit-point sets of uneven size. Each lane reads its set's
+// record (state buffer, payload and cell-start offsets) from a small device table, and everything
+// that changes between iterations (iteration index, J, lower bound) comes from the set's state, so
+// the launch can be replayed from a captured graph.
 //
 // Per pair inside the disk (Sec. 3.2, Sec. 5.1):
 //   y = (<x - x*, u>, <x - x*, v>)             (Eq. map-function)
 //   g = annulus (2 d2 >= r2) x sector (60 degree wedges from +u)
-//   S_g += psi, Q_g += psi^2                  (compensated float32 pairs)
+//   S_g += psi, Q_g += psi^2                  (compensated float32 pairs, TwoSum / fma product)
 //   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1)
 // Epilogue per kernel: retained sums (Sec. 5.1), F in float64 (Eq. f-statistic) against the
 // tabulated critical value for m = sum of J over the kept iterations, estimate update
@@ -94,13 +99,12 @@ constexpr int UNROLL = 4;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
 struct Lds {
-    float4 slot[NG][WAVE];        // lane-private S, comp S, Q, comp Q per group
+    float4 slot[NG][WAVE];        // lane-private pairs (S, err S, Q, err Q) per group
     float4 part[2][WAVE];         // lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
     uint32_t rs[WAVE];            // row start in the payload
     uint32_t ro[WAVE];            // row offset in the concatenation (exclusive)
     uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
     uint32_t queue[2 * WAVE];     // in-disk photons waiting for accumulation, 2 G slots per kernel
-    uint32_t hist[RHIST_BINS];
 };
 
 // Per-kernel constants of one work item, held in registers by the kernel's G lanes.
@@ -112,7 +116,7 @@ struct Query {
 // Accumulators of one lane.
 struct Acc {
     float fR, cR, fG, cG, fB, cB;
-    uint32_t cnt, ncand;
+    uint32_t cnt;
 };
 
 // Adds the photon pi (already inside the disk) to this lane's group sums and flux sum when it
@@ -151,40 +155,59 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
         wB = f.z;
     }
     float4 sv = L.slot[g][lane];
-    kahan(sv.x, sv.y, psi);
-    kahan(sv.z, sv.w, psi * psi);
+    acc2(sv.x, sv.y, psi);
+    acc2_sq(sv.z, sv.w, psi);
     L.slot[g][lane] = sv;
-    kahan(c.fR, c.cR, wR);
-    kahan(c.fG, c.cG, wG);
-    kahan(c.fB, c.cB, wB);
+    acc2(c.fR, c.cR, wR);
+    acc2(c.fG, c.cG, wG);
+    acc2(c.fB, c.cB, wB);
     ++c.cnt;
 }
 
-// Each kernel's G lanes take up to G queued photons (lane j the j-th); the rest move to the front.
+// Each kernel's G lanes take up to G queued photons; the rest move to the front. `head` counts the
+// kernel's photons accumulated so far (mod G): lane j takes the queued photon whose position in the
+// kernel's in-disk stream is congruent to j mod G, so every lane sums a fixed subsequence of the
+// stream whatever the drain times (which depend on the other kernels of the wave), and the result
+// of a kernel does not depend on its neighbours in the launch.
 template <int G, bool NRM, bool VCM>
-__device__ __forceinline__ void drain_once(uint32_t &qlen, int j, int base, const Query &K, float cos_min,
-                                           const float4 *rA, const float4 *rB, const float4 *rC, Lds &L, int lane,
-                                           Acc &c)
+__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j, int base, const Query &K,
+                                           float cos_min, const float4 *rA, const float4 *rB, const float4 *rC,
+                                           Lds &L, int lane, Acc &c)
 {
     __syncthreads();
     const uint32_t n = min(qlen, (uint32_t)G);
-    if ((uint32_t)j < n) accumulate<NRM, VCM>(L.queue[2 * base + j], K, cos_min, rA, rB, rC, L, lane, c);
+    const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
+    if (k < n) accumulate<NRM, VCM>(L.queue[2 * base + k], K, cos_min, rA, rB, rC, L, lane, c);
     const uint32_t rem = qlen - n;
     const uint32_t moved = ((uint32_t)j < rem) ? L.queue[2 * base + G + j] : 0u;
     __syncthreads();
     if ((uint32_t)j < rem) L.queue[2 * base + j] = moved;
     qlen = rem;
+    head = (head + n) & (uint32_t)(G - 1);
 }
 
 template <int G, bool NRM, bool VCM>
-__device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, bool active, uint64_t &pairs_acc,
-                                        uint64_t &cand_acc)
+__device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t entry, bool active)
 {
     const int lane = threadIdx.x;
     const int j = lane % G;
     const int base = lane - j;
-    const SetHeader *hdr = A.hdr;
-    const float4 *rA = A.payA, *rB = A.payB, *rC = A.payC;
+    // this lane's kernel: set record, then its arrays (slot k at arr + k * stride)
+    const uint32_t q = entry & ((1u << Q_BITS) - 1u);
+    const SetDesc D = A.desc[active ? (entry >> Q_BITS) : 0u];
+    char *const arr = D.state + D.arr;
+    auto fslot = [&](int k) { return reinterpret_cast<float *>(arr + (size_t)k * D.stride); };
+    auto uslot = [&](int k) { return reinterpret_cast<uint32_t *>(arr + (size_t)k * D.stride); };
+    auto dslot = [&](int k) { return reinterpret_cast<double *>(arr + (size_t)k * D.stride); };
+    const SetHeader *hdr = reinterpret_cast<const SetHeader *>(D.state + D.hdr);
+    const double *mprefix = reinterpret_cast<const double *>(D.state + D.mprefix);
+    const double *fctab = reinterpret_cast<const double *>(D.state + D.fctab);
+    const float *lbtab = reinterpret_cast<const float *>(D.state + D.lbtab);
+    // payload planes at a wave-uniform base; photon indices are global (set offset added per row)
+    const float4 *rA = A.pay, *rB = A.pay + A.pstride, *rC = A.pay + 2 * (size_t)A.pstride;
+    const uint32_t *cstart = A.cstart + D.cell_base;
+    const int iter = active ? hdr->iter : 1;
+    const float Jf = active ? hdr->Jf : 1.0f;
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
     const uint64_t below = (j == 0) ? 0ull : ((~0ull >> (64 - j)) << base);
 
@@ -200,28 +223,28 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
     if (active) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            K.p[a] = A.kp[a][q];
-            K.u[a] = A.ku[a][q];
-            K.v[a] = A.kv[a][q];
-            if (NRM) K.nv[a] = A.kn[a][q];
+            K.p[a] = fslot(SL_POS + a)[q];
+            K.u[a] = fslot(SL_U + a)[q];
+            K.v[a] = fslot(SL_V + a)[q];
+            if (NRM) K.nv[a] = fslot(SL_NRM + a)[q];
         }
-        r = A.r[q];
+        r = fslot(SL_R)[q];
     }
     K.r2 = active ? r * r : -1.0f;
     K.inv_eta = 0.0f;
     K.wc = 0.0f;
     if (VCM && active) {
-        const float eta = A.Jf * (PI_F * K.r2);       // n_VM / n_VC * pi r^2, n_VC = 1
+        const float eta = Jf * (PI_F * K.r2);         // n_VM / n_VC * pi r^2, n_VC = 1
         K.inv_eta = 1.0f / eta;
-        K.wc = fmaf(A.cdvm[q], INV_PI_F, A.cdvcm[q] * K.inv_eta);
-        K.cb[0] = A.cb[0][q];
-        K.cb[1] = A.cb[1][q];
-        K.cb[2] = A.cb[2][q];
+        K.wc = fmaf(fslot(SL_CDVM)[q], INV_PI_F, fslot(SL_CDVCM)[q] * K.inv_eta);
+        K.cb[0] = fslot(SL_CB)[q];
+        K.cb[1] = fslot(SL_CB + 1)[q];
+        K.cb[2] = fslot(SL_CB + 2)[q];
     }
 #pragma unroll
     for (int g = 0; g < NG; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u, 0u};
-    uint32_t qlen = 0;
+    Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+    uint32_t qlen = 0, head = 0;
 
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
     const bool any = active && stencil(hdr, K.p, r, c0, c1);
@@ -236,8 +259,9 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         if (row < nrows) {
             const uint32_t cy = (uint32_t)(c0[1] + row % nyr), cz = (uint32_t)(c0[2] + row / nyr);
             const uint32_t cell = (cz * dimy + cy) * dimx;
-            st = A.cstart[cell + (uint32_t)c0[0]];
-            len = A.cstart[cell + (uint32_t)c1[0] + 1u] - st;
+            const uint32_t s0 = cstart[cell + (uint32_t)c0[0]];
+            len = cstart[cell + (uint32_t)c1[0] + 1u] - s0;
+            st = s0 + D.pay_off;
         }
         const uint32_t inc = group_incl_scan<G>(len, j);
         const uint32_t total = __shfl(inc, base + G - 1, WAVE);
@@ -276,7 +300,6 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
             for (int u = 0; u < UNROLL; ++u) {
                 bool in = false;
                 if (pis[u] != 0xFFFFFFFFu) {
-                    ++c.ncand;
                     const float dx = K.p[0] - a[u].x, dy = K.p[1] - a[u].y, dz = K.p[2] - a[u].z;
                     const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     in = d2 < K.r2;
@@ -287,11 +310,12 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
                 if (in) L.queue[2 * base + qlen + before] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
                 if (__ballot(qlen >= (uint32_t)G) != 0ull)
-                    drain_once<G, NRM, VCM>(qlen, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+                    drain_once<G, NRM, VCM>(qlen, head, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
             }
         }
     }
-    while (__ballot(qlen > 0u) != 0ull) drain_once<G, NRM, VCM>(qlen, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+    while (__ballot(qlen > 0u) != 0ull)
+        drain_once<G, NRM, VCM>(qlen, head, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
 
     // Combine the G lane partials in lane order. Columns 0..11 are the groups, 12 and 13 the flux
     // pairs; lane j of the kernel combines columns j, j + G, ... (all of them in lane order).
@@ -306,31 +330,31 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         const int col = j + k * G;
         S[k] = cS[k] = Q[k] = cQ[k] = 0.0f;
         if (active && col < NG) {
-            S[k] = A.sq0[(size_t)(4 * col) * A.astride + q];
-            cS[k] = A.sq0[(size_t)(4 * col + 1) * A.astride + q];
-            Q[k] = A.sq0[(size_t)(4 * col + 2) * A.astride + q];
-            cQ[k] = A.sq0[(size_t)(4 * col + 3) * A.astride + q];
+            S[k] = fslot(SL_SQ + 4 * col)[q];
+            cS[k] = fslot(SL_SQ + 4 * col + 1)[q];
+            Q[k] = fslot(SL_SQ + 4 * col + 2)[q];
+            cQ[k] = fslot(SL_SQ + 4 * col + 3)[q];
         }
         if (col < COLS) {
             for (int l = 0; l < G; ++l) {
                 const float4 x = (col < NG) ? L.slot[col][base + l] : L.part[col - NG][base + l];
-                kahan(S[k], cS[k], x.x);
-                kahan(S[k], cS[k], -x.y);
-                kahan(Q[k], cQ[k], x.z);
-                kahan(Q[k], cQ[k], -x.w);
+                acc2(S[k], cS[k], x.x);
+                cS[k] += x.y;
+                acc2(Q[k], cQ[k], x.z);
+                cQ[k] += x.w;
             }
         }
     }
     const uint32_t cnt_q = group_sum_u<G>(c.cnt);
-    const uint32_t t_new = active ? A.t[q] + 1u : 1u;
-    const double m = active ? A.mprefix[A.iter] - A.mprefix[A.iter - (int)t_new] : 2.0;
+    const uint32_t t_new = active ? uslot(SL_T)[q] + 1u : 1u;
+    const double m = active ? mprefix[iter] - mprefix[iter - (int)t_new] : 2.0;
     double sg[CPL], qg[CPL];
     double tl = 0.0;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const bool grp = j + k * G < NG;
-        sg[k] = grp ? (double)S[k] - (double)cS[k] : 0.0;
-        qg[k] = grp ? (double)Q[k] - (double)cQ[k] : 0.0;
+        sg[k] = grp ? (double)S[k] + (double)cS[k] : 0.0;
+        qg[k] = grp ? (double)Q[k] + (double)cQ[k] : 0.0;
         tl += sg[k];
     }
     const double tot = group_sum<G>(tl);
@@ -346,18 +370,18 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
     const double ssb = group_sum<G>(bl) / m;
     const double ssw = group_sum<G>(wl);
     constexpr int K12 = NG / G, J12 = NG % G, K13 = (NG + 1) / G, J13 = (NG + 1) % G;
-    const float flR = __shfl(S[K12] - cS[K12], base + J12, WAVE);
-    const float flG = __shfl(Q[K12] - cQ[K12], base + J12, WAVE);
-    const float flB = __shfl(S[K13] - cS[K13], base + J13, WAVE);
+    const float flR = __shfl(S[K12] + cS[K12], base + J12, WAVE);
+    const float flG = __shfl(Q[K12] + cQ[K12], base + J12, WAVE);
+    const float flB = __shfl(S[K13] + cS[K13], base + J13, WAVE);
 
     int shrink = 0;
     if (active && j == 0) {
-        const uint32_t seen = A.nseen[q] + cnt_q;
+        const uint32_t seen = uslot(SL_NSEEN)[q] + cnt_q;
         const double F = (ssb / (NG - 1)) / (ssw / (NG * (m - 1.0)));
-        const double Fc = A.fctab[t_new];
+        const double Fc = fctab[t_new];
         shrink = (seen > 0u && ssw > 0.0 && m >= 2.0 && (F > Fc)) ? 1 : 0;
         // this iteration's kernel estimate with its own radius
-        const float denom = A.Jf * (PI_F * K.r2);
+        const float denom = Jf * (PI_F * K.r2);
         float eR = flR / denom, eG = flG / denom, eB = flB / denom;
         if (VCM) {
             eR = K.cb[0] * eR;
@@ -366,51 +390,45 @@ __device__ __forceinline__ void process(const GatherArgs &A, Lds &L, int64_t q, 
         }
         float tv[6];
 #pragma unroll
-        for (int cc = 0; cc < 6; ++cc) tv[cc] = A.tau0[(size_t)cc * A.astride + q];
-        kahan(tv[0], tv[1], eR);
-        kahan(tv[2], tv[3], eG);
-        kahan(tv[4], tv[5], eB);
+        for (int cc = 0; cc < 6; ++cc) tv[cc] = fslot(SL_TAU + cc)[q];
+        acc2(tv[0], tv[1], eR);
+        acc2(tv[2], tv[3], eG);
+        acc2(tv[4], tv[5], eB);
 #pragma unroll
-        for (int cc = 0; cc < 6; ++cc) A.tau0[(size_t)cc * A.astride + q] = tv[cc];
-        const float rn = shrink ? fmaxf(A.k * r, A.lb) : r;
-        A.r[q] = rn;
-        A.t[q] = shrink ? 0u : t_new;
-        A.nseen[q] = shrink ? 0u : seen;
-        A.cnt[q] = cnt_q;
-        A.dec[q] = shrink ? 1u : 0u;
-        A.F[q] = seen > 0u ? F : (double)NAN;
-        A.Fc[q] = Fc;
-        atomicAdd(&L.hist[radius_bin(rn, A.r1)], 1u);
+        for (int cc = 0; cc < 6; ++cc) fslot(SL_TAU + cc)[q] = tv[cc];
+        const float rn = shrink ? fmaxf(A.k * r, lbtab[iter + 1]) : r;
+        fslot(SL_R)[q] = rn;
+        uslot(SL_T)[q] = shrink ? 0u : t_new;
+        uslot(SL_NSEEN)[q] = shrink ? 0u : seen;
+        uslot(SL_CNT)[q] = cnt_q;
+        uslot(SL_DEC)[q] = shrink ? 1u : 0u;
+        dslot(SL_F)[q] = seen > 0u ? F : (double)NAN;
+        dslot(SL_FC)[q] = Fc;
     }
     shrink = __shfl(shrink, base, WAVE);
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
         if (active && col < NG) {
-            A.sq0[(size_t)(4 * col) * A.astride + q] = shrink ? 0.0f : S[k];
-            A.sq0[(size_t)(4 * col + 1) * A.astride + q] = shrink ? 0.0f : cS[k];
-            A.sq0[(size_t)(4 * col + 2) * A.astride + q] = shrink ? 0.0f : Q[k];
-            A.sq0[(size_t)(4 * col + 3) * A.astride + q] = shrink ? 0.0f : cQ[k];
+            fslot(SL_SQ + 4 * col)[q] = shrink ? 0.0f : S[k];
+            fslot(SL_SQ + 4 * col + 1)[q] = shrink ? 0.0f : cS[k];
+            fslot(SL_SQ + 4 * col + 2)[q] = shrink ? 0.0f : Q[k];
+            fslot(SL_SQ + 4 * col + 3)[q] = shrink ? 0.0f : cQ[k];
         }
     }
-    pairs_acc += c.cnt;
-    cand_acc += c.ncand;
     __syncthreads();
 }
 
 template <bool NRM, bool VCM, int GL, int GH>
-__global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
+__global__ __launch_bounds__(WAVE) void gather_update_kernel(BatchArgs A)
 {
     __shared__ Lds L;
     const int lane = threadIdx.x;
-    L.hist[lane] = 0;
-    __syncthreads();
     constexpr uint32_t KPW_L = WAVE / GL;     // light kernels per wave
     constexpr uint32_t KPW_H = WAVE / GH;     // heavy kernels per wave
     const uint32_t n_heavy = A.counts[0], n_light = A.counts[1];
     const uint32_t items_h = (n_heavy + KPW_H - 1) / KPW_H;
     const uint32_t n_items = items_h + (n_light + KPW_L - 1) / KPW_L;
-    uint64_t pairs = 0, cand = 0;
     // Workgroups are dealt to the 8 XCDs round-robin. Chunk k of XCD_CHUNK consecutive items (a
     // compact patch along the Morton order) goes to XCD k mod 8, and an XCD walks its chunks in
     // order, so each XCD's L2 holds the photons of a few patches instead of the whole scene. The
@@ -422,29 +440,17 @@ __global__ __launch_bounds__(WAVE) void gather_update_kernel(GatherArgs A)
         if (item < items_h) {
             const uint32_t hi = item * KPW_H + (uint32_t)(lane / GH);
             const bool act = hi < n_heavy;
-            process<GH, NRM, VCM>(A, L, act ? (int64_t)A.heavy[hi] : 0, act, pairs, cand);
+            process<GH, NRM, VCM>(A, L, act ? A.heavy[hi] : 0u, act);
         } else {
             const uint32_t li = (item - items_h) * KPW_L + (uint32_t)(lane / GL);
             const bool act = li < n_light;
-            process<GL, NRM, VCM>(A, L, act ? (int64_t)A.light[li] : 0, act, pairs, cand);
+            process<GL, NRM, VCM>(A, L, act ? A.light[li] : 0u, act);
         }
-    }
-    __syncthreads();
-    if (L.hist[lane]) atomicAdd(&A.hdr->rhist[lane], L.hist[lane]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        pairs += __shfl_xor(pairs, o, WAVE);
-        cand += __shfl_xor(cand, o, WAVE);
-    }
-    if (lane == 0) {
-        if (pairs) atomicAdd(&A.hdr->n_pairs, (unsigned long long)pairs);
-        if (cand) atomicAdd(&A.hdr->n_cand, (unsigned long long)cand);
-        if (blockIdx.x == 0) atomicAdd(&A.hdr->n_launch, 1ull);
     }
 }
 
 template <bool NRM, bool VCM>
-static void launch_lanes(const GatherArgs &a, int gl, int gh, int grid, hipStream_t s)
+static void launch_lanes(const BatchArgs &a, int gl, int gh, int grid, hipStream_t s)
 {
 #define HK_LAUNCH(GLV, GHV) gather_update_kernel<NRM, VCM, GLV, GHV><<<grid, WAVE, 0, s>>>(a)
     if (gh == 16) {
@@ -459,13 +465,13 @@ static void launch_lanes(const GatherArgs &a, int gl, int gh, int grid, hipStrea
 #undef HK_LAUNCH
 }
 
-void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)
+void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, hipStream_t s)
 {
-    if (a.H <= 0) return;
+    if (h_total <= 0) return;
     const int gl = (a.lanes_light == 4 || a.lanes_light == 8) ? a.lanes_light : 16;
     const int gh = (a.lanes_heavy == 16) ? 16 : 64;
     const int64_t per = 8 * (int64_t)XCD_CHUNK;
-    const int grid = (int)(cdiv(cdiv(a.H, WAVE / gl), per) * per);
+    const int grid = (int)(cdiv(cdiv(h_total, WAVE / gl), per) * per);
     if (nrm && vcm)
         launch_lanes<true, true>(a, gl, gh, grid, s);
     else if (nrm)
@@ -477,17 +483,20 @@ void launch_gather(const GatherArgs &a, bool nrm, bool vcm, hipStream_t s)
 }
 
 // ------------------------------------------------------------------------------------------------
-// work list: cost of a kernel = photons in its stencil; heavy kernels (cost > heavy_cost) first
+// work list: cost of a kernel = photons in its stencil; heavy kernels (cost > heavy_cost) first.
+// Each set writes its kernels' flags and entries at its offset in the batch; one scan and one split
+// over the whole batch give the heavy list and the light list, both in set order.
 // ------------------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= l.H) return;
+    const int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in = q0 < l.H;
+    const int64_t q = in ? q0 : l.H - 1;
     const float p[3] = {l.kp[0][q], l.kp[1][q], l.kp[2][q]};
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
     uint32_t cost = 0;
-    if (stencil(l.hdr, p, l.r[q], c0, c1)) {
+    if (in && stencil(l.hdr, p, l.r[q], c0, c1)) {
         const uint32_t dimx = (uint32_t)l.hdr->dims[0], dimy = (uint32_t)l.hdr->dims[1];
         for (int cz = c0[2]; cz <= c1[2]; ++cz)
             for (int cy = c0[1]; cy <= c1[1]; ++cy) {
@@ -496,54 +505,127 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
             }
     }
     const uint32_t h = cost > l.heavy_cost ? 1u : 0u;
-    l.flag[q] = h;
-    l.offs[q] = h;
+    if (in) {
+        l.flag[q] = h;
+        l.offs[q] = h;
+        l.ids[q] = (l.set_slot << Q_BITS) | (uint32_t)q;
+    }
+    // candidate tests of this iteration (every photon of the stencil is tested once): one atomic
+    // per wavefront, issued at the end of the kernel
+    unsigned long long v = cost;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && v) atomicAdd(&l.hdr->n_cand, v);
 }
 
-__global__ __launch_bounds__(256) void split_kernel(ListLaunch l)
+void launch_cost(const ListLaunch &l, hipStream_t s)
+{
+    if (l.H <= 0) return;
+    cost_kernel<<<(int)cdiv(l.H, 256), 256, 0, s>>>(l);
+}
+
+__global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const uint32_t *offs, const uint32_t *ids,
+                                                    int64_t n, uint32_t *heavy, uint32_t *light, uint32_t *counts)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= l.H) return;
-    const uint32_t o = l.offs[q];
-    if (l.flag[q])
-        l.heavy[o] = (uint32_t)q;
+    if (q >= n) return;
+    const uint32_t o = offs[q];
+    if (flag[q])
+        heavy[o] = ids[q];
     else
-        l.light[(uint32_t)q - o] = (uint32_t)q;
-    if (q == l.H - 1) {
-        const uint32_t nh = o + l.flag[q];
-        l.counts[0] = nh;
-        l.counts[1] = (uint32_t)l.H - nh;
+        light[(uint32_t)q - o] = ids[q];
+    if (q == n - 1) {
+        const uint32_t nh = o + flag[q];
+        counts[0] = nh;
+        counts[1] = (uint32_t)n - nh;
     }
 }
 
-void build_work_list(const ListLaunch &l, hipStream_t s)
+void launch_split(uint32_t *flag, uint32_t *offs, uint32_t *ids, int64_t n, uint32_t *part, uint32_t *heavy,
+                  uint32_t *light, uint32_t *counts, hipStream_t s)
 {
-    const int nb = (int)cdiv(l.H, 256);
-    cost_kernel<<<nb, 256, 0, s>>>(l);
-    excl_scan(l.offs, l.H, l.part2, s);
-    split_kernel<<<nb, 256, 0, s>>>(l);
+    if (n <= 0) return;
+    excl_scan(offs, n, part, s);
+    split_kernel<<<(int)cdiv(n, 256), 256, 0, s>>>(flag, offs, ids, n, heavy, light, counts);
+}
+
+// ------------------------------------------------------------------------------------------------
+// after the update: per set, the histogram of the new radii (the next plan's cell size) and the
+// in-disk pairs of the iteration. The work list's entries are in set order, so a block's range
+// belongs to one set except at set boundaries; the block tallies its first set in LDS and adds any
+// other set's entries directly.
+// ------------------------------------------------------------------------------------------------
+
+constexpr int TALLY_PER_BLOCK = 4096;
+
+__global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const uint32_t *ids, int64_t n)
+{
+    __shared__ uint32_t hist[RHIST_BINS];
+    __shared__ unsigned long long pairs;
+    const int64_t b0 = (int64_t)blockIdx.x * TALLY_PER_BLOCK;
+    const int64_t b1 = min(n, b0 + (int64_t)TALLY_PER_BLOCK);
+    const uint32_t set0 = ids[b0] >> Q_BITS;
+    const SetDesc D0 = desc[set0];
+    SetHeader *h0 = reinterpret_cast<SetHeader *>(D0.state + D0.hdr);
+    const float r1_0 = h0->r1;
+    if (threadIdx.x < RHIST_BINS) hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) pairs = 0ull;
+    __syncthreads();
+    unsigned long long acc = 0;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) {
+        const uint32_t id = ids[e];
+        const uint32_t set = id >> Q_BITS, q = id & ((1u << Q_BITS) - 1u);
+        if (set == set0) {
+            const char *arr = D0.state + D0.arr;
+            const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D0.stride)[q];
+            acc += reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D0.stride)[q];
+            atomicAdd(&hist[radius_bin(r, r1_0)], 1u);
+        } else {
+            const SetDesc D = desc[set];
+            SetHeader *h = reinterpret_cast<SetHeader *>(D.state + D.hdr);
+            const char *arr = D.state + D.arr;
+            const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D.stride)[q];
+            const uint32_t c = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D.stride)[q];
+            atomicAdd(&h->rhist[radius_bin(r, h->r1)], 1u);
+            if (c) atomicAdd(&h->n_pairs, (unsigned long long)c);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && acc) atomicAdd(&pairs, acc);
+    __syncthreads();
+    if (threadIdx.x < RHIST_BINS && hist[threadIdx.x]) atomicAdd(&h0->rhist[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 0 && pairs) atomicAdd(&h0->n_pairs, pairs);
+}
+
+void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s)
+{
+    if (h_total <= 0) return;
+    tally_kernel<<<(int)cdiv(h_total, TALLY_PER_BLOCK), 256, 0, s>>>(desc, ids, h_total);
 }
 
 // ------------------------------------------------------------------------------------------------
 // critical values: fctab[t] = (1 - alpha_F) quantile of F(11, 12 (m_t - 1)), m_t = J of the last t
-// iterations (Sec. 3.2.2); no test (NaN) when m_t < 2
+// iterations (Sec. 3.2.2); no test (NaN) when m_t < 2. The iteration index is read from the set
+// header (advanced by the plan kernel). With `all` every t = 1..iter is recomputed (J changed at
+// some point); otherwise only t = iter is new, since with a constant J the earlier entries hold.
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void fcrit_kernel(double *fctab, const double *mprefix, int iter, int t_lo,
-                                                   int t_hi, double alpha)
+__global__ __launch_bounds__(64) void fcrit_kernel(const SetHeader *hdr, double *fctab, const double *mprefix,
+                                                   int all, double alpha)
 {
-    const int t = t_lo + (int)(blockIdx.x * 64 + threadIdx.x);
-    if (t > t_hi) return;
+    const int iter = hdr->iter;
+    const int t = all ? 1 + (int)(blockIdx.x * 64 + threadIdx.x) : iter;
+    if (t > iter || (!all && (blockIdx.x != 0 || threadIdx.x != 0))) return;
     const double m = mprefix[iter] - mprefix[iter - t];
     fctab[t] = (m >= 2.0) ? f_quantile((double)(NG - 1), (double)NG * (m - 1.0), alpha) : (double)NAN;
 }
 
-void launch_fcrit(double *fctab, const double *mprefix, int iter, int t_lo, int t_hi, double alpha_f,
-                  hipStream_t s)
+void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all,
+                  double alpha_f, hipStream_t s)
 {
-    if (t_hi < t_lo) return;
-    const int n = t_hi - t_lo + 1;
-    fcrit_kernel<<<(int)cdiv(n, 64), 64, 0, s>>>(fctab, mprefix, iter, t_lo, t_hi, alpha_f);
+    const int nb = all ? (int)cdiv(max_iters, 64) : 1;
+    fcrit_kernel<<<nb, 64, 0, s>>>(hdr, fctab, mprefix, all ? 1 : 0, alpha_f);
 }
 
 }  // namespace hk

@@ -195,11 +195,17 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
 // per-iteration grid
 // ------------------------------------------------------------------------------------------------
 
-// One thread: append J to the prefix sums, choose the cell size from the radius histogram.
-__global__ void plan_kernel(SetHeader *hdr, double *mprefix, int iter, double J, float cell_scale, float quantile,
+// One thread: advance the set's iteration counter, append J to the prefix sums, choose the cell size
+// from the radius histogram. Everything that changes between iterations lives in the state, so a
+// captured graph can replay the iteration.
+__global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile,
                             uint32_t max_cells)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int iter = hdr->iter + 1;
+    hdr->iter = iter;
+    hdr->Jf = (float)J;
+    hdr->n_launch += 1ull;
     mprefix[iter] = mprefix[iter - 1] + J;
     const double target = (double)quantile * hdr->H;
     double cum = 0.0;
@@ -386,6 +392,8 @@ __global__ __launch_bounds__(1024) void bbox_kernel(SetHeader *hdr, double *mpre
         hdr->n_launch = 0;
         hdr->n_pairs = 0;
         hdr->n_cand = 0;
+        hdr->iter = 0;
+        hdr->Jf = 0.0f;
     }
     for (int i = threadIdx.x; i < max_iters + 2; i += 1024) mprefix[i] = 0.0;
 }
@@ -416,11 +424,11 @@ __global__ __launch_bounds__(256) void morton_kernel(const SetHeader *hdr, const
     keys[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
 }
 
-__global__ __launch_bounds__(256) void init_state_kernel(KernelSrc src, StateView st, const uint32_t *perm,
-                                                         int64_t n, float r1, int nsq)
+// One hit point s of the Morton-ordered set: copy, tangent frame, cleared statistics; its radius
+// goes to the block's histogram.
+__device__ void init_one(const KernelSrc &src, const StateView &st, const uint32_t *perm, int64_t s, float r1,
+                         uint32_t *hist)
 {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
     const uint32_t j = perm[s];
     for (int a = 0; a < 3; ++a) st.pos[a][s] = src.pos[a][j];
     float nv[3] = {0.0f, 0.0f, 1.0f};
@@ -440,8 +448,8 @@ __global__ __launch_bounds__(256) void init_state_kernel(KernelSrc src, StateVie
     st.orig[s] = j;
     st.cnt[s] = 0;
     st.dec[s] = 0;
-    for (int i = 0; i < nsq; ++i) st.sq[i][s] = 0.0f;
-    for (int i = 0; i < 6; ++i) st.tau[i][s] = 0.0f;
+    for (int i = 0; i < NSQ; ++i) st.sq0[(size_t)i * st.astride + s] = 0.0f;
+    for (int i = 0; i < 6; ++i) st.tau0[(size_t)i * st.astride + s] = 0.0f;
     st.F[s] = NAN;
     st.Fc[s] = NAN;
     if (src.cam_beta[0]) {
@@ -449,7 +457,19 @@ __global__ __launch_bounds__(256) void init_state_kernel(KernelSrc src, StateVie
         st.cdvcm[s] = src.cam_mis[0][j];
         st.cdvm[s] = src.cam_mis[2][j];
     }
-    atomicAdd(&st.hdr->rhist[radius_bin(r, r1)], 1u);
+    atomicAdd(&hist[radius_bin(r, r1)], 1u);
+}
+
+__global__ __launch_bounds__(256) void init_state_kernel(KernelSrc src, StateView st, const uint32_t *perm,
+                                                         int64_t n, float r1)
+{
+    __shared__ uint32_t hist[RHIST_BINS];
+    if (threadIdx.x < RHIST_BINS) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < n) init_one(src, st, perm, s, r1, hist);
+    __syncthreads();
+    if (threadIdx.x < RHIST_BINS && hist[threadIdx.x]) atomicAdd(&st.hdr->rhist[threadIdx.x], hist[threadIdx.x]);
 }
 
 void init_set(const InitLaunch &g, hipStream_t s)
@@ -461,15 +481,41 @@ void init_set(const InitLaunch &g, hipStream_t s)
     morton_kernel<<<nb, 256, 0, s>>>(g.st.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
     uint32_t *ks, *vs;
     radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs);
-    init_state_kernel<<<nb, 256, 0, s>>>(g.src, g.st, vs, n, g.r1, g.nsq);
+    init_state_kernel<<<nb, 256, 0, s>>>(g.src, g.st, vs, n, g.r1);
 }
 
 }  // namespace hk
 
 namespace hk {
-void launch_plan(SetHeader *hdr, double *mprefix, int iter, double J, float cell_scale, float quantile,
-                 uint32_t max_cells, hipStream_t s)
+void launch_plan(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile, uint32_t max_cells,
+                 hipStream_t s)
 {
-    plan_kernel<<<1, 64, 0, s>>>(hdr, mprefix, iter, J, cell_scale, quantile, max_cells);
+    plan_kernel<<<1, 64, 0, s>>>(hdr, mprefix, J, cell_scale, quantile, max_cells);
 }
+// Small host tables (the set records of a batch, the radius lower bounds) travel to the device in
+// kernel arguments, UPLOAD_WORDS words per launch: the copy is ordered on the stream, needs no host
+// buffer that outlives the call, and is an ordinary kernel node when the sequence is captured.
+constexpr int UPLOAD_WORDS = 128;
+struct UploadChunk {
+    uint32_t w[UPLOAD_WORDS];
+};
+
+__global__ __launch_bounds__(UPLOAD_WORDS) void upload_kernel(uint32_t *dst, UploadChunk c, int n)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.w[threadIdx.x];
+}
+
+void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    const uint32_t *w = static_cast<const uint32_t *>(src);
+    uint32_t *d = static_cast<uint32_t *>(dst);
+    for (size_t i = 0; i < n; i += UPLOAD_WORDS) {
+        UploadChunk c{};
+        const int k = (int)((n - i < (size_t)UPLOAD_WORDS) ? n - i : (size_t)UPLOAD_WORDS);
+        for (int j = 0; j < k; ++j) c.w[j] = w[i + j];
+        upload_kernel<<<1, UPLOAD_WORDS, 0, s>>>(d + i, c, k);
+    }
+}
+
 }  // namespace hk

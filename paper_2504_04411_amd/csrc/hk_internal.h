@@ -14,8 +14,8 @@ constexpr int RHIST_BINS = 64;      // radius histogram: bin = floor(-4 log2(r /
 constexpr uint32_t KEY_OUTSIDE = 0xFFFFFFu;   // cell key of a photon outside the grid domain
 constexpr uint32_t MAX_CELLS = 0xFFFFF0u;     // keys fit 24 bits: three 8-bit radix passes
 constexpr int WAVE = 64;            // wavefront width of gfx950
-constexpr int G_LIGHT = 16;         // lanes per kernel in a light work item (4 kernels per wave)
-constexpr int G_HEAVY = 64;         // lanes per kernel in a heavy work item (1 kernel per wave)
+constexpr int MAX_BATCH = 64;       // sets gathered by one launch (6 bits of a work-list entry)
+constexpr uint32_t Q_BITS = 26;     // kernel index bits of a work-list entry
 constexpr float PI_F = 3.14159265358979323846f;
 constexpr float INV_PI_F = 0.31830988618379067f;
 
@@ -39,30 +39,35 @@ struct SetHeader {
     int32_t dims[3];
     uint32_t ncells;
     float cell;
-    int32_t pad[4];
+    int32_t iter;            // iterations started (the plan kernel advances it)
+    float Jf;                // J_emitted of the current iteration
+    int32_t pad[2];
     // running totals since hk_set_kernels (gather launches, in-disk pairs, lane x photon tests)
     unsigned long long n_launch;
     unsigned long long n_pairs;
     unsigned long long n_cand;
 };
 
-// Offsets (bytes) of every array of a set's state; each array is 256-byte aligned.
-struct Layout {
-    int64_t H = 0;
-    int max_iters = 0;
-    size_t hdr = 0, mprefix = 0, fctab = 0;
-    size_t pos[3] = {}, nrm[3] = {}, u[3] = {}, v[3] = {};
-    size_t r = 0, t = 0, nseen = 0, orig = 0, cnt = 0, dec = 0;
-    size_t sq[NSQ * 3] = {};    // luminance test uses the first NSQ; per-channel test all 3 x NSQ
-    size_t tau[6] = {};         // R, comp R, G, comp G, B, comp B
-    size_t F = 0, Fc = 0;
-    size_t cb[3] = {}, cdvcm = 0, cdvm = 0;
-    size_t total = 0;
+// Per-kernel arrays of a set's state, by slot: every slot is `stride` bytes (256-byte aligned, one
+// float or uint32 per kernel); float64 arrays take two slots.
+enum Slot : int {
+    SL_POS = 0, SL_NRM = 3, SL_U = 6, SL_V = 9, SL_R = 12, SL_T = 13, SL_NSEEN = 14, SL_ORIG = 15, SL_CNT = 16,
+    SL_DEC = 17, SL_SQ = 18, SL_TAU = SL_SQ + NSQ, SL_F = SL_TAU + 6, SL_FC = SL_F + 2, SL_CB = SL_FC + 2,
+    SL_CDVCM = SL_CB + 3, SL_CDVM = SL_CDVCM + 1, SL_COUNT = SL_CDVM + 1
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-inline Layout make_layout(int64_t H, int max_iters, bool rgb_stats)
+// Offsets (bytes) in a set's state buffer.
+struct Layout {
+    int64_t H = 0;
+    int max_iters = 0;
+    size_t hdr = 0, mprefix = 0, fctab = 0, lbtab = 0, arr = 0, stride = 0, total = 0;
+    size_t slot(int k) const { return arr + (size_t)k * stride; }
+};
+
+inline Layout make_layout(int64_t H, int max_iters)
 {
     Layout L;
     L.H = H;
@@ -72,26 +77,10 @@ inline Layout make_layout(int64_t H, int max_iters, bool rgb_stats)
     L.hdr = take(sizeof(SetHeader));
     L.mprefix = take(sizeof(double) * (max_iters + 2));
     L.fctab = take(sizeof(double) * (max_iters + 2));
-    const size_t f = sizeof(float) * (size_t)H;
-    for (int a = 0; a < 3; ++a) L.pos[a] = take(f);
-    for (int a = 0; a < 3; ++a) L.nrm[a] = take(f);
-    for (int a = 0; a < 3; ++a) L.u[a] = take(f);
-    for (int a = 0; a < 3; ++a) L.v[a] = take(f);
-    L.r = take(f);
-    L.t = take(f);
-    L.nseen = take(f);
-    L.orig = take(f);
-    L.cnt = take(f);
-    L.dec = take(f);
-    const int nsq = rgb_stats ? 3 * NSQ : NSQ;
-    for (int i = 0; i < nsq; ++i) L.sq[i] = take(f);
-    for (int i = 0; i < 6; ++i) L.tau[i] = take(f);
-    L.F = take(2 * f);
-    L.Fc = take(2 * f);
-    for (int a = 0; a < 3; ++a) L.cb[a] = take(f);
-    L.cdvcm = take(f);
-    L.cdvm = take(f);
-    L.total = off;
+    L.lbtab = take(sizeof(float) * (max_iters + 2));
+    L.stride = align256(sizeof(float) * (size_t)H);
+    L.arr = off;
+    L.total = L.arr + (size_t)SL_COUNT * L.stride;
     return L;
 }
 
@@ -100,11 +89,13 @@ struct StateView {
     SetHeader *hdr;
     double *mprefix;     // mprefix[i] = sum of J over iterations 1..i
     double *fctab;       // fctab[t] = critical value for t kept iterations
+    float *lbtab;        // lbtab[i] = r_min sqrt(i^(alpha-1)), float32
     float *pos[3], *nrm[3], *u[3], *v[3];
     float *r;
     uint32_t *t, *nseen, *orig, *cnt, *dec;
-    float *sq[NSQ * 3];
-    float *tau[6];
+    float *sq0;          // group sums: array k at sq0 + k * astride
+    float *tau0;         // estimate: array c at tau0 + c * astride
+    uint32_t astride;    // floats between slots
     double *F, *Fc;
     float *cb[3], *cdvcm, *cdvm;
 };
@@ -112,39 +103,46 @@ struct StateView {
 inline StateView make_view(void *base, const Layout &L)
 {
     char *b = static_cast<char *>(base);
+    auto f = [&](int k) { return reinterpret_cast<float *>(b + L.slot(k)); };
+    auto u = [&](int k) { return reinterpret_cast<uint32_t *>(b + L.slot(k)); };
     StateView s;
     s.hdr = reinterpret_cast<SetHeader *>(b + L.hdr);
     s.mprefix = reinterpret_cast<double *>(b + L.mprefix);
     s.fctab = reinterpret_cast<double *>(b + L.fctab);
+    s.lbtab = reinterpret_cast<float *>(b + L.lbtab);
     for (int a = 0; a < 3; ++a) {
-        s.pos[a] = reinterpret_cast<float *>(b + L.pos[a]);
-        s.nrm[a] = reinterpret_cast<float *>(b + L.nrm[a]);
-        s.u[a] = reinterpret_cast<float *>(b + L.u[a]);
-        s.v[a] = reinterpret_cast<float *>(b + L.v[a]);
-        s.cb[a] = reinterpret_cast<float *>(b + L.cb[a]);
+        s.pos[a] = f(SL_POS + a);
+        s.nrm[a] = f(SL_NRM + a);
+        s.u[a] = f(SL_U + a);
+        s.v[a] = f(SL_V + a);
+        s.cb[a] = f(SL_CB + a);
     }
-    s.r = reinterpret_cast<float *>(b + L.r);
-    s.t = reinterpret_cast<uint32_t *>(b + L.t);
-    s.nseen = reinterpret_cast<uint32_t *>(b + L.nseen);
-    s.orig = reinterpret_cast<uint32_t *>(b + L.orig);
-    s.cnt = reinterpret_cast<uint32_t *>(b + L.cnt);
-    s.dec = reinterpret_cast<uint32_t *>(b + L.dec);
-    for (int i = 0; i < NSQ * 3; ++i) s.sq[i] = L.sq[i] ? reinterpret_cast<float *>(b + L.sq[i]) : nullptr;
-    for (int i = 0; i < 6; ++i) s.tau[i] = reinterpret_cast<float *>(b + L.tau[i]);
-    s.F = reinterpret_cast<double *>(b + L.F);
-    s.Fc = reinterpret_cast<double *>(b + L.Fc);
-    s.cdvcm = reinterpret_cast<float *>(b + L.cdvcm);
-    s.cdvm = reinterpret_cast<float *>(b + L.cdvm);
+    s.r = f(SL_R);
+    s.t = u(SL_T);
+    s.nseen = u(SL_NSEEN);
+    s.orig = u(SL_ORIG);
+    s.cnt = u(SL_CNT);
+    s.dec = u(SL_DEC);
+    s.sq0 = f(SL_SQ);
+    s.tau0 = f(SL_TAU);
+    s.astride = (uint32_t)(L.stride / sizeof(float));
+    s.F = reinterpret_cast<double *>(b + L.slot(SL_F));
+    s.Fc = reinterpret_cast<double *>(b + L.slot(SL_FC));
+    s.cdvcm = f(SL_CDVCM);
+    s.cdvm = f(SL_CDVM);
     return s;
 }
 
-// Workspace carve-up for one set's iteration (or for the kernel ordering in hk_set_kernels).
-struct WsLayout {
-    int64_t max_photons = 0, max_kernels = 0;
-    uint32_t max_cells = 0;
-    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, cstart = 0, pay = 0;
-    size_t flag = 0, offs = 0, part2 = 0, part3 = 0, heavy = 0, light = 0, counts = 0;
-    size_t total = 0;
+// Per-set record read by the batched gather (device table in the workspace).
+struct SetDesc {
+    char *state;             // state base
+    uint64_t arr;            // byte offset of slot 0
+    uint64_t stride;         // bytes per slot
+    uint32_t H;
+    uint32_t pay_off;        // first photon of the set in the combined payload
+    uint32_t cell_base;      // first cell start of the set in the combined cell-start array
+    uint32_t max_iters;
+    uint64_t mprefix, fctab, lbtab, hdr;   // byte offsets in the state
 };
 
 constexpr int RS_THREADS = 256;
@@ -154,37 +152,67 @@ constexpr int SCAN_TILE = 4096;                    // counters per scan block
 // sorted payload, three float4 per photon: (x, y, z, luminance), (nx, ny, nz, dVM), (R, G, B, dVCM)
 constexpr int PAY_VEC = 3;
 
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline uint32_t max_cells_for(int64_t n_photons)
+{
+    int64_t mc = 4 * (n_photons > 1024 ? n_photons : 1024);
+    if (mc > (int64_t)MAX_CELLS) mc = MAX_CELLS;
+    return (uint32_t)mc;
+}
 
-inline WsLayout make_ws_layout(int64_t max_photons, int64_t max_kernels)
+// Workspace of one batched iteration (or of the kernel ordering in hk_set_kernels).
+struct WsLayout {
+    int n_sets = 0;
+    int64_t n_total = 0, h_total = 0, n_max = 0;
+    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
+    size_t cstart = 0, pay = 0;
+    size_t flag = 0, offs = 0, ids = 0, part2 = 0, heavy = 0, light = 0, counts = 0, desc = 0;
+    uint32_t pay_off[MAX_BATCH] = {}, cell_base[MAX_BATCH] = {}, max_cells[MAX_BATCH] = {};
+    uint32_t q_off[MAX_BATCH] = {};
+    size_t total = 0;
+};
+
+inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64_t *n_kernels)
 {
     WsLayout W;
-    int64_t n = max_photons > max_kernels ? max_photons : max_kernels;
-    if (n < 1) n = 1;
-    W.max_photons = max_photons;
-    W.max_kernels = max_kernels;
-    int64_t mc = 4 * (max_photons > 1024 ? max_photons : 1024);
-    if (mc > (int64_t)MAX_CELLS) mc = MAX_CELLS;
-    W.max_cells = (uint32_t)mc;
+    W.n_sets = n_sets;
+    int64_t nmax = 1, cells = 0;
+    // with more than MAX_BATCH sets only the sizes are meaningful (a bound for any batch of them)
+    for (int s = 0; s < n_sets; ++s) {
+        const uint32_t mc = max_cells_for(n_photons[s]);
+        if (s < MAX_BATCH) {
+            W.pay_off[s] = (uint32_t)W.n_total;
+            W.q_off[s] = (uint32_t)W.h_total;
+            W.cell_base[s] = (uint32_t)cells;
+            W.max_cells[s] = mc;
+        }
+        cells += (int64_t)mc + 2;
+        W.n_total += n_photons[s];
+        W.h_total += n_kernels[s];
+        if (n_photons[s] > nmax) nmax = n_photons[s];
+        if (n_kernels[s] > nmax) nmax = n_kernels[s];
+    }
+    W.n_max = nmax;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    W.keyA = take(4 * (size_t)n);
-    W.keyB = take(4 * (size_t)n);
-    W.valA = take(4 * (size_t)n);
-    W.valB = take(4 * (size_t)n);
-    int64_t nblk = cdiv(n, RS_TILE);
+    W.keyA = take(4 * (size_t)nmax);
+    W.keyB = take(4 * (size_t)nmax);
+    W.valA = take(4 * (size_t)nmax);
+    W.valB = take(4 * (size_t)nmax);
+    const int64_t nblk = cdiv(nmax, RS_TILE);
     W.hist = take(4 * (size_t)(256 * nblk));
     W.part = take(4 * (size_t)(cdiv(256 * nblk, SCAN_TILE) + 1));
-    W.cstart = take(4 * (size_t)(W.max_cells + 2));
-    W.part3 = take(4 * (size_t)(cdiv((int64_t)W.max_cells + 1, SCAN_TILE) + 1));
-    W.pay = take(16 * (size_t)max_photons * PAY_VEC + 256);
-    const size_t hk = 4 * (size_t)(max_kernels + 1);
+    W.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
+    W.cstart = take(4 * (size_t)(cells + 1));
+    W.pay = take(16 * (size_t)W.n_total * PAY_VEC + 256);     // plane stride: n_total photons
+    const size_t hk = 4 * (size_t)(W.h_total + 1);
     W.flag = take(hk);
     W.offs = take(hk);
-    W.part2 = take(4 * (size_t)(cdiv(max_kernels + 1, SCAN_TILE) + 1));
+    W.ids = take(hk);
+    W.part2 = take(4 * (size_t)(cdiv(W.h_total + 1, SCAN_TILE) + 1));
     W.heavy = take(hk);
     W.light = take(hk);
     W.counts = take(64);
+    W.desc = take(sizeof(SetDesc) * MAX_BATCH);
     W.total = off;
     return W;
 }
@@ -228,13 +256,26 @@ __device__ __forceinline__ float luminance(float R, float G, float B)
     return fmaf(0.0722f, B, fmaf(0.7152f, G, 0.2126f * R));
 }
 
-// Compensated (Kahan) accumulation: (s - c) tracks the exact running sum to O(n u^2).
-__device__ __forceinline__ void kahan(float &s, float &c, float x)
+// Compensated float32 accumulation into a pair (s, c) that stands for s + c: Knuth's TwoSum gives
+// the rounding error e of s + x exactly (s + x = t + e), and c collects those errors (the Neumaier
+// form of compensated summation). Unlike the classic Kahan update, the error of forming x - c is not
+// lost, so the pair tracks the exact sum to about n u^2 of its magnitude instead of u per term.
+__device__ __forceinline__ void acc2(float &s, float &c, float x)
 {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
+    const float t = s + x;
+    const float z = t - s;
+    const float e = (s - (t - z)) + (x - z);
     s = t;
+    c += e;
+}
+
+// Adds x^2 to the pair exactly up to the pair's own rounding: the product's error comes from an fma
+// (x * x = p + fma(x, x, -p) exactly).
+__device__ __forceinline__ void acc2_sq(float &s, float &c, float x)
+{
+    const float p = x * x;
+    acc2(s, c, p);
+    c += fmaf(x, x, -p);
 }
 
 // Radius histogram bin: floor(-4 log2(r / r1)) clamped to the table.

@@ -92,7 +92,8 @@ class Estimator:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self.ws
 
-    def set_kernels(self, set_id: int, pos, nrm=None, r_init=None, cam_beta=None, cam_mis=None):
+    def set_kernels(self, set_id: int, pos, nrm=None, r_init=None, cam_beta=None, cam_mis=None, r1=None, rmin=None):
+        """Uploads a hit-point set; r1 / rmin give the set its own radius scale (default: the context's)."""
         pos_t = _dev(pos, self.device)
         n = int(pos_t.shape[1])
         nrm_t, cb_t, cm_t = _dev(nrm, self.device), _dev(cam_beta, self.device), _dev(cam_mis, self.device)
@@ -100,21 +101,50 @@ class Estimator:
         st = torch.empty(hk.hk_state_bytes(self.ctx, n), dtype=torch.uint8, device=self.device)
         wsb = hk.hk_workspace_bytes(self.ctx, 0, n)
         ws = self._workspace(wsb)
-        hk.hk_set_kernels(self.ctx, set_id, n, _rows(pos_t), _rows(nrm_t), None if r_t is None else r_t.data_ptr(),
-                          _rows(cb_t), _rows(cm_t), st.data_ptr(), ws.data_ptr(), ws.numel(), self.stream)
+        hk.hk_set_kernels(self.ctx, set_id, n, -1.0 if r1 is None else r1, -1.0 if rmin is None else rmin,
+                          _rows(pos_t), _rows(nrm_t), None if r_t is None else r_t.data_ptr(), _rows(cb_t),
+                          _rows(cm_t), st.data_ptr(), ws.data_ptr(), ws.numel(), self.stream)
         self.states[set_id] = st
         self.n[set_id] = n
         self.inputs[set_id] = [pos_t, nrm_t, cb_t, cm_t, r_t]     # kept alive until the stream passes
         return st
 
     def workspace_for(self, photons: Sequence[DevicePhotons], set_ids: Sequence[int]) -> int:
-        return max(hk.hk_workspace_bytes(self.ctx, ph.n, self.n[s]) for s, ph in zip(set_ids, photons))
+        return hk.hk_workspace_bytes_batch(self.ctx, [ph.n for ph in photons], [self.n[s] for s in set_ids])
 
     def iterate(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]):
+        """One iteration of the given sets; their gathers share launches (up to 64 sets each)."""
         wsb = self.workspace_for(photons, set_ids)
         ws = self._workspace(wsb)
         hk.hk_iterate(self.ctx, list(set_ids), [p.struct() for p in photons],
                       [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel(), self.stream)
+
+    def capture(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]) -> "Graph":
+        """Captures one iteration of the sets into a graph; refill `photons` in place between launches."""
+        wsb = self.workspace_for(photons, set_ids)
+        ws = self._workspace(wsb)
+        g = hk.hk_graph_create(self.ctx, list(set_ids), [p.struct() for p in photons],
+                               [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel())
+        return Graph(self, g, ws, list(photons))
+
+    def autotune(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]) -> dict:
+        """Times the candidate settings on scratch copies of the states and keeps the fastest."""
+        wsb = self.workspace_for(photons, set_ids)
+        ws = self._workspace(wsb)
+        scratch = [torch.empty_like(self.states[s]) for s in set_ids]
+        p = hk.hk_autotune(self.ctx, list(set_ids), [ph.struct() for ph in photons],
+                           [self.states[s].data_ptr() for s in set_ids], [t.data_ptr() for t in scratch],
+                           ws.data_ptr(), ws.numel(), self.stream)
+        return dict(cell_scale=p.cell_scale, heavy_cost=p.heavy_cost, lanes_light=p.lanes_light,
+                    lanes_heavy=p.lanes_heavy)
+
+    def set_tuning(self, cell_scale=0.0, heavy_cost=0, lanes_light=0, lanes_heavy=0):
+        hk.hk_set_tuning(self.ctx, cell_scale, heavy_cost, lanes_light, lanes_heavy)
+
+    def tuning(self) -> dict:
+        p = hk.hk_get_params(self.ctx)
+        return dict(cell_scale=p.cell_scale, heavy_cost=p.heavy_cost, lanes_light=p.lanes_light,
+                    lanes_heavy=p.lanes_heavy)
 
     # ---- reads (device tensors, original kernel order) -------------------------------------------
     def radiance(self, set_id: int) -> torch.Tensor:
@@ -151,7 +181,7 @@ class Estimator:
         out = torch.zeros(4, dtype=torch.int64, device=self.device)
         hk.hk_read_stats(self.ctx, set_id, self.states[set_id].data_ptr(), out.data_ptr(), self.stream)
         v = out.cpu().tolist()
-        return dict(launches=v[0], pairs=v[1], candidates=v[2], cells=v[3])
+        return dict(iterations=v[0], pairs=v[1], candidates=v[2], cells=v[3])
 
     def profile(self, on: bool = True):
         hk.hk_profile_enable(self.ctx, on)
@@ -159,3 +189,24 @@ class Estimator:
     def profile_read(self) -> dict:
         v = hk.hk_profile_read(self.ctx)
         return dict(grid_ms=v[0], fcrit_ms=v[1], gather_ms=v[2], launches=int(v[3]))
+
+
+class Graph:
+    """A captured iteration (hk_graph): launch() runs one more iteration of its sets."""
+
+    def __init__(self, est: Estimator, handle: int, ws: torch.Tensor, photons):
+        self.est, self.handle, self.ws, self.photons = est, handle, ws, photons
+
+    def launch(self):
+        hk.hk_graph_launch(self.handle, self.est.stream)
+
+    def close(self):
+        if self.handle:
+            hk.hk_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

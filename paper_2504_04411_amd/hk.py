@@ -68,8 +68,18 @@ def lib():
             "hk_destroy": ([_vp], c.c_int),
             "hk_state_bytes": ([_vp, c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
             "hk_workspace_bytes": ([_vp, c.c_int64, c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
-            "hk_set_kernels": ([_vp, c.c_int, c.c_int64, _vp * 3, c.c_void_p, _vp, c.c_void_p, c.c_void_p,
-                                _vp, _vp, c.c_size_t, _vp], c.c_int),
+            "hk_workspace_bytes_batch": ([_vp, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
+                                          c.POINTER(c.c_size_t)], c.c_int),
+            "hk_get_params": ([_vp, c.POINTER(hk_params)], c.c_int),
+            "hk_set_tuning": ([_vp, c.c_float, c.c_int, c.c_int, c.c_int], c.c_int),
+            "hk_graph_create": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp,
+                                 c.c_size_t, c.POINTER(_vp)], c.c_int),
+            "hk_graph_launch": ([_vp, _vp], c.c_int),
+            "hk_graph_destroy": ([_vp], c.c_int),
+            "hk_autotune": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp),
+                             c.POINTER(_vp), _vp, c.c_size_t, _vp, c.POINTER(hk_params)], c.c_int),
+            "hk_set_kernels": ([_vp, c.c_int, c.c_int64, c.c_double, c.c_double, _vp * 3, c.c_void_p, _vp,
+                                c.c_void_p, c.c_void_p, _vp, _vp, c.c_size_t, _vp], c.c_int),
             "hk_iterate": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp,
                             c.c_size_t, _vp], c.c_int),
             "hk_read_radiance": ([_vp, c.c_int, _vp, _vp * 3, _vp], c.c_int),
@@ -152,7 +162,27 @@ def hk_workspace_bytes(ctx: int, max_photons: int, max_kernels: int) -> int:
     return out.value
 
 
-def hk_set_kernels(ctx, set_id, n, pos, nrm, r_init, cam_beta, cam_mis, state, workspace, workspace_bytes, stream):
+def hk_workspace_bytes_batch(ctx: int, n_photons, n_kernels) -> int:
+    n = len(n_photons)
+    out = ctypes.c_size_t()
+    a = (ctypes.c_int64 * n)(*[int(x) for x in n_photons])
+    b = (ctypes.c_int64 * n)(*[int(x) for x in n_kernels])
+    check(lib().hk_workspace_bytes_batch(ctx, n, a, b, ctypes.byref(out)))
+    return out.value
+
+
+def hk_get_params(ctx: int) -> hk_params:
+    p = hk_params()
+    check(lib().hk_get_params(ctx, ctypes.byref(p)))
+    return p
+
+
+def hk_set_tuning(ctx: int, cell_scale: float, heavy_cost: int, lanes_light: int, lanes_heavy: int):
+    check(lib().hk_set_tuning(ctx, float(cell_scale), int(heavy_cost), int(lanes_light), int(lanes_heavy)))
+
+
+def hk_set_kernels(ctx, set_id, n, r1, rmin, pos, nrm, r_init, cam_beta, cam_mis, state, workspace, workspace_bytes,
+                   stream):
     keep = []
     args = []
     for x in (nrm, cam_beta, cam_mis):
@@ -162,8 +192,8 @@ def hk_set_kernels(ctx, set_id, n, pos, nrm, r_init, cam_beta, cam_mis, state, w
         else:
             args.append(o[0])
             keep.append(o[1])
-    check(lib().hk_set_kernels(ctx, int(set_id), int(n), _arr3(pos), args[0], r_init, args[1], args[2], state,
-                               workspace, int(workspace_bytes), stream))
+    check(lib().hk_set_kernels(ctx, int(set_id), int(n), float(r1), float(rmin), _arr3(pos), args[0], r_init,
+                               args[1], args[2], state, workspace, int(workspace_bytes), stream))
 
 
 def make_photons(J_emitted, n_stored, pos, flux, nrm=None, mis=None) -> hk_photons:
@@ -183,6 +213,34 @@ def hk_iterate(ctx, set_ids, photons, states, workspace, workspace_bytes, stream
     phs = (hk_photons * n)(*photons)
     sts = (_vp * n)(*states)
     check(lib().hk_iterate(ctx, n, ids, phs, sts, workspace, int(workspace_bytes), stream))
+
+
+def _set_arrays(set_ids, photons, states):
+    n = len(set_ids)
+    return (n, (ctypes.c_int * n)(*set_ids), (hk_photons * n)(*photons), (_vp * n)(*states))
+
+
+def hk_graph_create(ctx, set_ids, photons, states, workspace, workspace_bytes) -> int:
+    n, ids, phs, sts = _set_arrays(set_ids, photons, states)
+    g = _vp()
+    check(lib().hk_graph_create(ctx, n, ids, phs, sts, workspace, int(workspace_bytes), ctypes.byref(g)))
+    return g.value
+
+
+def hk_graph_launch(graph, stream):
+    check(lib().hk_graph_launch(graph, stream))
+
+
+def hk_graph_destroy(graph):
+    check(lib().hk_graph_destroy(graph))
+
+
+def hk_autotune(ctx, set_ids, photons, states, scratch, workspace, workspace_bytes, stream) -> hk_params:
+    n, ids, phs, sts = _set_arrays(set_ids, photons, states)
+    scr = (_vp * n)(*scratch)
+    p = hk_params()
+    check(lib().hk_autotune(ctx, n, ids, phs, sts, scr, workspace, int(workspace_bytes), stream, ctypes.byref(p)))
+    return p
 
 
 def hk_read_radiance(ctx, set_id, state, out_rgb, stream):

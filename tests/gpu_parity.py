@@ -38,6 +38,7 @@ class ParityReport:
     max_Fc_rel: float = 0.0
     max_L_rel: float = 0.0
     excluded: int = 0
+    worst_F: dict = field(default_factory=dict)
     notes: list = field(default_factory=list)
 
 
@@ -63,56 +64,87 @@ def _rel(a, b):
     return d
 
 
+class Tracker:
+    """Oracle run of one set (kernels idx) checked against the GPU set `set_id` after each iteration."""
+
+    def __init__(self, w: G.Workload, idx=None, name=None):
+        self.w, self.p = w, w.params
+        ks = w.kernels
+        self.idx = np.arange(ks.n) if idx is None else np.asarray(idx)
+        self.oks = sub_kernels(ks, self.idx)
+        self.ost = O.init_state(self.idx.size, self.p.r1)
+        self.alive = np.ones(self.idx.size, bool)
+        self.rep = ParityReport(kernels=self.idx.size)
+        self.name = name or w.name
+
+    def step(self, est: Estimator, set_id: int, ph):
+        """Advances the oracle by the iteration the GPU just ran with photons ph and compares."""
+        idx, ost, alive, rep = self.idx, self.ost, self.alive, self.rep
+        it = rep.iterations
+        O.iterate(self.p, self.oks, ost, ph)
+        d = {k: v.cpu().numpy()[idx] for k, v in est.debug(set_id).items()}
+        rg = est.radii(set_id).cpu().numpy()[idx]
+        cnt = d["count"].astype(np.uint32)
+        bad = np.flatnonzero(alive & (cnt != ost.count))
+        assert bad.size == 0, (f"[{self.name}] iteration {it + 1}: count mismatch at {idx[bad[:5]]}: "
+                               f"{cnt[bad[:5]]} vs {ost.count[bad[:5]]}")
+        band = np.abs(ost.F - ost.Fc) < BAND
+        dg = d["decision"].astype(bool)
+        diff = alive & (dg != ost.shrink)
+        assert not np.any(diff & ~band), \
+            f"[{self.name}] iteration {it + 1}: decision mismatch outside the band at {idx[diff & ~band][:5]}"
+        rep.band_cases += int((alive & band).sum())
+        rep.band_flips += int(diff.sum())
+        alive &= ~diff
+        rep.shrinks += int((alive & ost.shrink).sum())
+        badr = np.flatnonzero(alive & (rg != ost.r))
+        assert badr.size == 0, (f"[{self.name}] iteration {it + 1}: radius mismatch at {idx[badr[:5]]}: "
+                                f"{rg[badr[:5]]} vs {ost.r[badr[:5]]}")
+        fr = _err_F(d["F"], ost.F)[alive]
+        assert np.all(np.isnan(d["F"][alive]) == np.isnan(ost.F[alive])), f"[{self.name}] F defined on one side only"
+        if fr.size and np.nanmax(fr) > rep.max_F_rel:
+            k = np.flatnonzero(alive)[int(np.nanargmax(fr))]
+            rep.max_F_rel = float(fr[int(np.nanargmax(fr))])
+            rep.worst_F = dict(iteration=it + 1, kernel=int(idx[k]), F_gpu=float(d["F"][k]), F_oracle=float(ost.F[k]),
+                               Fc=float(ost.Fc[k]), count=int(ost.count[k]), m=float(ost.m[k]))
+        fin = alive & np.isfinite(ost.Fc)
+        if fin.any():
+            rep.max_Fc_rel = max(rep.max_Fc_rel, float(_rel(d["Fc"][fin], ost.Fc[fin]).max()))
+        rep.iterations += 1
+
+    def finish(self, est: Estimator, set_id: int) -> ParityReport:
+        rep, alive, idx = self.rep, self.alive, self.idx
+        assert rep.max_F_rel < 2e-7, rep
+        assert rep.max_Fc_rel < 1e-10, rep
+        Lg = est.radiance(set_id).cpu().numpy()[:, idx].T
+        Lo = O.radiance(self.ost)
+        lr = _rel(Lg[alive], Lo[alive])
+        rep.max_L_rel = float(lr.max()) if lr.size else 0.0
+        assert rep.max_L_rel < 1e-5, rep
+        rep.excluded = int((~alive).sum())
+        assert rep.excluded <= max(2, idx.size // 1000), rep
+        return rep
+
+
+def make_estimator(w: G.Workload, **est_kw) -> Estimator:
+    p = w.params
+    return Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin, **est_kw)
+
+
 def run_parity(w: G.Workload, n_iter: int, idx=None, photons_fn=None, est_kw=None, verbose=True) -> ParityReport:
     """Runs n_iter iterations on the GPU (all kernels) and on the oracle (kernels idx, default all)."""
-    p = w.params
     ks = w.kernels
-    idx = np.arange(ks.n) if idx is None else np.asarray(idx)
-    est = Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin, **(est_kw or {}))
+    est = make_estimator(w, **(est_kw or {}))
     est.set_kernels(0, ks.pos, ks.nrm, None, ks.cam_beta, ks.cam_mis)
-    oks = sub_kernels(ks, idx)
-    ost = O.init_state(idx.size, p.r1)
-    alive = np.ones(idx.size, bool)
-    rep = ParityReport(kernels=idx.size)
+    tr = Tracker(w, idx)
     get = photons_fn or w.photons
     for it in range(n_iter):
         ph = get(it)
         if verbose:
             print(f"  [{w.name}] iteration {it + 1}/{n_iter}: H={ks.n} J={ph.J} stored={ph.n}", flush=True)
         est.iterate([0], [DevicePhotons.upload(ph)])
-        O.iterate(p, oks, ost, ph)
-        d = {k: v.cpu().numpy()[idx] for k, v in est.debug(0).items()}
-        rg = est.radii(0).cpu().numpy()[idx]
-        cnt = d["count"].astype(np.uint32)
-        bad = np.flatnonzero(alive & (cnt != ost.count))
-        assert bad.size == 0, f"iteration {it + 1}: count mismatch at {idx[bad[:5]]}: {cnt[bad[:5]]} vs {ost.count[bad[:5]]}"
-        band = np.abs(ost.F - ost.Fc) < BAND
-        dg = d["decision"].astype(bool)
-        diff = alive & (dg != ost.shrink)
-        assert not np.any(diff & ~band), f"iteration {it + 1}: decision mismatch outside the band at {idx[diff & ~band][:5]}"
-        rep.band_cases += int((alive & band).sum())
-        rep.band_flips += int(diff.sum())
-        alive &= ~diff
-        rep.shrinks += int((alive & ost.shrink).sum())
-        badr = np.flatnonzero(alive & (rg != ost.r))
-        assert badr.size == 0, f"iteration {it + 1}: radius mismatch at {idx[badr[:5]]}: {rg[badr[:5]]} vs {ost.r[badr[:5]]}"
-        fr = _err_F(d["F"], ost.F)[alive]
-        assert np.all(np.isnan(d["F"][alive]) == np.isnan(ost.F[alive])), "F defined on one side only"
-        if fr.size:
-            rep.max_F_rel = max(rep.max_F_rel, float(np.nanmax(fr)))
-        fin = alive & np.isfinite(ost.Fc)
-        if fin.any():
-            rep.max_Fc_rel = max(rep.max_Fc_rel, float(_rel(d["Fc"][fin], ost.Fc[fin]).max()))
-        rep.iterations += 1
-    assert rep.max_F_rel < 2e-7, rep
-    assert rep.max_Fc_rel < 1e-10, rep
-    Lg = est.radiance(0).cpu().numpy()[:, idx].T
-    Lo = O.radiance(ost)
-    lr = _rel(Lg[alive], Lo[alive])
-    rep.max_L_rel = float(lr.max()) if lr.size else 0.0
-    assert rep.max_L_rel < 1e-5, rep
-    rep.excluded = int((~alive).sum())
-    assert rep.excluded <= max(2, idx.size // 1000), rep
+        tr.step(est, 0, ph)
+    rep = tr.finish(est, 0)
     est.close()
     if verbose:
         print(f"  parity ok: {rep}", flush=True)
