@@ -20,6 +20,8 @@
  *     message for the calling thread. No call aborts the process.
  *   - Calls taking a hipStream_t only enqueue work on that stream; they do not synchronise (except
  *     where stated). The caller keeps every buffer alive until the stream has passed the call.
+ *     hk_iterate and graphs fork part of an iteration onto a stream the context owns and join it
+ *     back, so all of it stays ordered after earlier and before later work on the caller's stream.
  *   - Pointers named "device" must be device memory of the context's GPU; "host" pointers are read
  *     during the call only.
  *   - The library allocates no device memory. The caller allocates the per-set state and the shared
@@ -196,8 +198,9 @@ double hk_f_quantile(double d1, double d2, double alpha);
 
 /* Timing of the hk_iterate calls since enabling (hipEvents on the caller's stream; graphs are not
  * timed): hk_profile_enable(ctx, 1) starts recording, hk_profile_read(ctx, out, n) synchronises on
- * the last event and writes up to n phase totals in milliseconds: [0] grid builds, [1] critical
- * values, [2] work list + gather + test + update, [3] gather launches counted. */
+ * the last event and writes up to n phase totals in milliseconds: [0] iteration plans and grid
+ * builds, [1] wait for the critical values beyond the grid builds (they run on a second stream
+ * beside them), [2] work list + gather + test + update + tally, [3] gather launches counted. */
 int hk_profile_enable(hk_ctx *ctx, int on);
 int hk_profile_read(hk_ctx *ctx, double *out, int n);
 

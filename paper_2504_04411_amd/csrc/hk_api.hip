@@ -65,6 +65,8 @@ struct hk_ctx {
     bool prof = false;
     std::vector<ProfEv> ev_used, ev_free;
     hipStream_t cap = nullptr;     // stream used for graph capture (created on first use)
+    hipStream_t aux = nullptr;     // second stream: critical values run beside the grid builds
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct hk_graph {
@@ -163,6 +165,9 @@ extern "C" int hk_destroy(hk_ctx *ctx)
         for (auto &pe : *v)
             for (auto e : pe.e) (void)hipEventDestroy(e);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
     delete ctx;
     return HK_OK;
 }
@@ -386,6 +391,14 @@ static void advance(SetInfo &S, uint64_t J)
     S.iter += 1;
 }
 
+static int ensure_streams(hk_ctx *ctx)
+{
+    if (!ctx->aux) HIP_TRY(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    if (!ctx->join) HIP_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    return HK_OK;
+}
+
 // Enqueues one iteration of every set (no host bookkeeping: the caller advances the sets).
 static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
                    void *workspace, size_t workspace_bytes, hipStream_t stream, bool prof, const char *all_in,
@@ -400,6 +413,8 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             return fail(HK_E_SMALL_BUFFER, "workspace of %zu bytes, %zu needed", workspace_bytes, W.total);
     }
     if (all_out) all_out->assign(n_sets, 0);
+    int rc = ensure_streams(ctx);
+    if (rc) return rc;
     char *w = static_cast<char *>(workspace);
     for (const auto &b : batches) {
         const WsLayout W = batch_layout(ctx, b, set_ids, ph);
@@ -410,14 +425,34 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         if (pe) HIP_TRY(hipEventRecord(pe->e[0], stream));
         uint32_t *ws_cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
         float4 *ws_pay = reinterpret_cast<float4 *>(w + W.pay);
-        // 1. per set: advance the iteration on the device, choose the cell size, sort the photons
+        // 1. per set: advance the iteration on the device and choose the cell size
+        for (int k = 0; k < nb; ++k) {
+            const int s = b[k];
+            const SetInfo &S = ctx->sets[set_ids[s]];
+            const StateView st = make_view(state[s], layout_of(ctx, S.H));
+            launch_plan(st.hdr, st.mprefix, (double)ph[s].J_emitted, p.cell_scale, p.cell_quantile, W.max_cells[k],
+                        stream);
+        }
+        // 2. critical values for the kept-iteration counts this iteration can reach, on the second
+        //    stream: they need only the plan's iteration index and J sums, and run beside the grids
+        HIP_TRY(hipEventRecord(ctx->fork, stream));
+        HIP_TRY(hipStreamWaitEvent(ctx->aux, ctx->fork, 0));
+        for (int k = 0; k < nb; ++k) {
+            const int s = b[k];
+            const SetInfo &S = ctx->sets[set_ids[s]];
+            const StateView st = make_view(state[s], layout_of(ctx, S.H));
+            const bool all = all_in ? all_in[s] != 0 : fcrit_all(S, ph[s].J_emitted);
+            if (all_out) (*all_out)[s] = all ? 1 : 0;
+            launch_fcrit(st.hdr, st.fctab, st.mprefix, p.max_iters, all, p.alpha_f, ctx->aux);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(ctx->join, ctx->aux));
+        // 3. per set: sort the photons into the grid
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
             const hk_photons &P = ph[s];
             const StateView st = make_view(state[s], layout_of(ctx, S.H));
-            launch_plan(st.hdr, st.mprefix, (double)P.J_emitted, p.cell_scale, p.cell_quantile, W.max_cells[k],
-                        stream);
             GridLaunch g{};
             g.hdr = st.hdr;
             for (int a = 0; a < 3; ++a) {
@@ -441,17 +476,9 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             build_grid(g, stream);
         }
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
-        // 2. per set: critical values for the kept-iteration counts this iteration can reach
-        for (int k = 0; k < nb; ++k) {
-            const int s = b[k];
-            const SetInfo &S = ctx->sets[set_ids[s]];
-            const StateView st = make_view(state[s], layout_of(ctx, S.H));
-            const bool all = all_in ? all_in[s] != 0 : fcrit_all(S, ph[s].J_emitted);
-            if (all_out) (*all_out)[s] = all ? 1 : 0;
-            launch_fcrit(st.hdr, st.fctab, st.mprefix, p.max_iters, all, p.alpha_f, stream);
-        }
+        HIP_TRY(hipStreamWaitEvent(stream, ctx->join, 0));
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
-        // 3. one work list over the batch, the set table, one gather / test / update launch, then the
+        // 4. one work list over the batch, the set table, one gather / test / update launch, then the
         //    radius histograms and pair counts of the batch's sets
         uint32_t *flag = reinterpret_cast<uint32_t *>(w + W.flag);
         uint32_t *offs = reinterpret_cast<uint32_t *>(w + W.offs);
@@ -541,6 +568,8 @@ extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, cons
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    rc = ensure_streams(ctx);
+    if (rc) return rc;
     hk_graph *g = new (std::nothrow) hk_graph();
     if (!g) return fail(HK_E_INVALID_ARG, "out of host memory");
     g->ctx = ctx;
