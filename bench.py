@@ -166,8 +166,9 @@ def main():
                                f"per iteration, point light and sphere occluder, {K} iterations",
                    "H": H, "J": args.photons, "iterations": K, "seed": args.seed},
         "gather_test_update_queries_per_s": round(H * K / gather_s, 1),
-        "phase_ms_total": {"grid": round(prof["grid_ms"], 3), "fcrit": round(prof["fcrit_ms"], 3),
-                           "gather_test_update": round(prof["gather_ms"], 3)},
+        "phase_ms_total": {"plan_and_grid": round(prof["grid_ms"], 3), "fcrit_wait": round(prof["fcrit_wait_ms"], 3),
+                           "work_list": round(prof["list_ms"], 3), "gather_test_update": round(prof["gather_ms"], 3),
+                           "tally": round(prof["tally_ms"], 3)},
         "pairs_per_query": round(stats["pairs"] / (H * K), 2),
         "candidates_per_pair": round(stats["candidates"] / max(stats["pairs"], 1), 3),
         "final_radius": {"mean": float(radii.mean()), "min": float(radii.min()),

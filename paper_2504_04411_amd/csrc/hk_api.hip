@@ -51,8 +51,9 @@ struct SetInfo {
     uint64_t J_first = 0;
 };
 
+constexpr int PROF_EVENTS = 6;   // start, grids, critical values joined, list, gather, tally
 struct ProfEv {
-    hipEvent_t e[4];
+    hipEvent_t e[PROF_EVENTS];
 };
 
 }  // namespace
@@ -534,9 +535,11 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         a.cos_min = p.normal_cos_min;
         a.lanes_light = p.lanes_light;
         a.lanes_heavy = p.lanes_heavy;
-        launch_gather(a, W.h_total, nrm_test, vcm, stream);
-        launch_tally(table, ids, W.h_total, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[3], stream));
+        launch_gather(a, W.h_total, nrm_test, vcm, stream);
+        if (pe) HIP_TRY(hipEventRecord(pe->e[4], stream));
+        launch_tally(table, ids, W.h_total, stream);
+        if (pe) HIP_TRY(hipEventRecord(pe->e[5], stream));
         HIP_TRY(hipGetLastError());
     }
     return HK_OK;
@@ -846,16 +849,16 @@ extern "C" int hk_profile_read(hk_ctx *ctx, double *out, int n)
 {
     if (!ctx || !out || n < 0) return fail(HK_E_INVALID_ARG, "bad arguments");
     HIP_TRY(hipSetDevice(ctx->device));
-    if (!ctx->ev_used.empty()) HIP_TRY(hipEventSynchronize(ctx->ev_used.back().e[3]));
-    double acc[4] = {0, 0, 0, 0};   // grid, critical values, list + gather, batches
+    if (!ctx->ev_used.empty()) HIP_TRY(hipEventSynchronize(ctx->ev_used.back().e[PROF_EVENTS - 1]));
+    double acc[PROF_EVENTS] = {};   // phase totals, then the number of batches
     for (auto &pe : ctx->ev_used) {
         float ms;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k + 1 < PROF_EVENTS; ++k) {
             HIP_TRY(hipEventElapsedTime(&ms, pe.e[k], pe.e[k + 1]));
             acc[k] += ms;
         }
-        acc[3] += 1.0;
+        acc[PROF_EVENTS - 1] += 1.0;
     }
-    for (int k = 0; k < n && k < 4; ++k) out[k] = acc[k];
+    for (int k = 0; k < n && k < PROF_EVENTS; ++k) out[k] = acc[k];
     return HK_OK;
 }

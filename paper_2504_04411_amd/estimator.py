@@ -188,7 +188,8 @@ class Estimator:
 
     def profile_read(self) -> dict:
         v = hk.hk_profile_read(self.ctx)
-        return dict(grid_ms=v[0], fcrit_ms=v[1], gather_ms=v[2], launches=int(v[3]))
+        return dict(grid_ms=v[0], fcrit_wait_ms=v[1], list_ms=v[2], gather_ms=v[3], tally_ms=v[4],
+                    launches=int(v[5]))
 
 
 class Graph:

@@ -272,8 +272,8 @@ def hk_profile_enable(ctx, on: bool):
 
 
 def hk_profile_read(ctx):
-    out = (ctypes.c_double * 4)()
-    check(lib().hk_profile_read(ctx, out, 4))
+    out = (ctypes.c_double * 6)()
+    check(lib().hk_profile_read(ctx, out, 6))
     return list(out)
 
 
