@@ -253,6 +253,50 @@ int oracle_gather_grid(const oracle_args *A, int nthreads)
     return 0;
 }
 
+/* Features of the learned radius proposal (not part of the paper's method): for each kernel, the
+ * light vertices inside the disks of radius R_s = r1 / 2^s, s = 0..3, counted in 8 equi-areal
+ * rings per scale. Ring b of scale s holds b/8 <= d2 / R_s^2 < (b+1)/8, decided in float32 against
+ * the thresholds R_s^2 * (k / 8), k = 1..7. Inside-disk and normal tests as in the gather.
+ * counts: H x 32, row-major (scale-major within a row). All pairs, in photon order. */
+int oracle_features(int64_t H, const float *kx, const float *ky, const float *kz, const float *knx,
+                    const float *kny, const float *knz, int64_t J, const float *px, const float *py,
+                    const float *pz, const float *pnx, const float *pny, const float *pnz, float r1,
+                    float cos_min, uint32_t *counts, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t h = 0; h < H; ++h) {
+        float R2[4], T[4][8];
+        for (int s = 0; s < 4; ++s) {
+            float R = r1 * (1.0f / (float)(1 << s));
+            R2[s] = R * R;
+            for (int k = 1; k < 8; ++k) T[s][k] = R2[s] * (0.125f * (float)k);
+        }
+        uint32_t *c = counts + h * 32;
+        memset(c, 0, 32 * sizeof(uint32_t));
+        for (int64_t j = 0; j < J; ++j) {
+            float dx = kx[h] - px[j];
+            float dy = ky[h] - py[j];
+            float dz = kz[h] - pz[j];
+            float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            if (!(d2 < R2[0])) continue;
+            if (knx && pnx) {
+                float cs = fmaf(knz[h], pnz[j], fmaf(kny[h], pny[j], knx[h] * pnx[j]));
+                if (!(cs >= cos_min)) continue;
+            }
+            for (int s = 0; s < 4; ++s) {
+                if (!(d2 < R2[s])) break;
+                int b = 0;
+                for (int k = 1; k < 8; ++k) b += (d2 >= T[s][k]) ? 1 : 0;
+                c[s * 8 + b] += 1;
+            }
+        }
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP
