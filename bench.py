@@ -63,6 +63,45 @@ def _gen(args):
     return it, b
 
 
+def _gen3(args):
+    seed, it, res, J, n = args
+    from workloads import generators as G
+    return it, G.config3(seed, res=res, J=J, n_iter=n).photons(it)
+
+
+def learned_vs_plain(args, ex):
+    """The learned radius proposal against the plain method at equal MSE on jittered box scenes:
+    trained on seeds 30-33, margin picked on seed 34, compared on the held-out seed 39."""
+    import torch
+    from paper_2504_04411_amd import learned as Lr
+    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+    from workloads import generators as G
+    res, J, n = args.res, args.photons, 64
+
+    def make_scene(seed):
+        w = G.config3(seed, res=res, J=J, n_iter=n)
+        out = [None] * n
+        for it, b in ex.map(_gen3, [(seed, i, res, J, n) for i in range(n)]):
+            out[it] = DevicePhotons.upload(b)
+        return w, out
+
+    p = G.config3(30, res=8, J=1000).params
+    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    out = Lr.experiment(est, make_scene, (30, 31, 32, 33), 34, 39,
+                        log=lambda m: print("# learned: " + m, file=sys.stderr, flush=True))
+    est.close()
+    torch.cuda.synchronize()
+    keep = {k: out[k] for k in ("plain_final_mse", "learned_final_mse", "iterations", "plain_ms", "learned_ms",
+                                "learned_iters_to_plain_final_mse", "learned_ms_to_plain_final_mse", "margin",
+                                "train_mse", "label_var", "train_rows")}
+    t = out["learned_ms_to_plain_final_mse"]
+    keep["speedup_to_plain_final_mse"] = round(out["plain_ms"] / t, 3) if t else None
+    keep["workload"] = (f"box scenes with jittered light and occluder, {res}x{res} hit points, {J} light paths per "
+                        f"iteration, {n} iterations; trained on seeds 30-33, margin from seed 34, compared on seed 39; "
+                        f"MSE of the radiance against the analytic direct light")
+    return keep
+
+
 def make_batches(seed, n, J, workers):
     out = [None] * n
     with ProcessPoolExecutor(max_workers=workers) as ex:
@@ -96,6 +135,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed job, copy a MIB-sized device buffer once (reference for HBM "
@@ -175,6 +215,9 @@ def main():
                          "shrunk_frac": float((radii < np.float32(p.r1)).mean())},
         "roofline": roof,
     }
+    if not args.no_learned:
+        with ProcessPoolExecutor(max_workers=args.workers) as ex:
+            out["learned_vs_plain"] = learned_vs_plain(args, ex)
     if not args.no_cpu_baseline:
         nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         q, secs, nk = cpu_baseline(w, batches[:K], args.cpu_stride, nthreads)

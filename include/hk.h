@@ -170,6 +170,57 @@ int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *p
                 void *const *scratch, void *workspace, size_t workspace_bytes, hipStream_t stream,
                 hk_params *chosen);
 
+/* ---- learned radius proposal (an addition to the paper's method; the F-test keeps judging) ------
+ * Features of a hit point: the light vertices of one batch in 8 equi-areal rings (ring b holds
+ * b/8 <= d^2/R^2 < (b+1)/8) at the four radii R = r1, r1/2, r1/4, r1/8, with the gather's inside-disk
+ * and normal tests; encoded as log1p(count) / 8, then the hit point's normal (3) and an iteration
+ * code (1): 36 bfloat16 values per hit point (uint16 bit patterns, row-major n x 36). Network: 36 ->
+ * 64 -> 64 -> 1 with ReLU, weights in bfloat16 on the matrix cores, float32 biases and accumulation,
+ * trained for the mean squared error by Adam (beta1 0.9, beta2 0.999, eps 1e-8) on float32 master
+ * parameters. Parameter vector (float32, hk_mlp_param_count() = 6593 values): W1 (36 x 64, row =
+ * input), b1 (64), W2 (64 x 64, row = input), b2 (64), w3 (64), b3. The network state (device,
+ * hk_mlp_state_bytes, 256-byte aligned) is owned by the caller. */
+int hk_mlp_param_count(void);
+int hk_mlp_state_bytes(size_t *out);
+
+/* Device workspace of hk_mlp_grad / hk_mlp_train_step for n samples. */
+int hk_mlp_workspace_bytes(int64_t n, size_t *out);
+
+/* Loads parameters (device float32 array of hk_mlp_param_count values) and clears Adam's moments
+ * and step count. */
+int hk_mlp_set_params(hk_ctx *ctx, void *mlp, const float *theta, hipStream_t stream);
+
+/* Copies the float32 master parameters to theta_out (device). */
+int hk_mlp_get_params(hk_ctx *ctx, const void *mlp, float *theta_out, hipStream_t stream);
+
+/* y[i] = network(feat[i]) for n samples (device arrays). */
+int hk_mlp_forward(hk_ctx *ctx, const void *mlp, const uint16_t *feat, int64_t n, float *y, hipStream_t stream);
+
+/* Gradient of the mean squared error (1/n) sum (y_i - label_i)^2 over the n samples, written to
+ * grad_out (device, hk_mlp_param_count() + 1 floats: the gradient, then the sum of squared errors);
+ * no update. workspace: hk_mlp_workspace_bytes(n). */
+int hk_mlp_grad(hk_ctx *ctx, const void *mlp, const uint16_t *feat, const float *label, int64_t n, float *grad_out,
+                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One Adam step on the mean squared error of the n samples (one mini-batch) with learning rate lr. */
+int hk_mlp_train_step(hk_ctx *ctx, void *mlp, const uint16_t *feat, const float *label, int64_t n, float lr,
+                      void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Features of set set_id's hit points from one batch of light vertices *ph (sorted into a grid of
+ * cell r1 in the workspace, hk_workspace_bytes(ctx, n_stored, H)); it_code is the last input of
+ * every row. feat (device, H x 36 bfloat16) and counts (device, H x 32 uint32, or NULL) are in the
+ * caller's original hit-point order. The set's iteration state is not changed. */
+int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_photons *ph, float it_code, uint16_t *feat,
+                    uint32_t *counts, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Proposal for the set's next iteration i + 1 from network outputs y (device, H floats, original
+ * order, predicting log(r / r1)): r <- min(max(r1 exp(y + margin), lb_{i+1}), r) in float32, so a
+ * radius never grows and never drops below the bound of Eq. radiusupdate; margin > 0 proposes
+ * larger radii than predicted (the F-test can still shrink them, never grow them). Hit points whose
+ * radius changes start their retained statistics afresh (t = 0, sums 0); the estimate so far is
+ * kept. */
+int hk_mlp_propose(hk_ctx *ctx, int set_id, void *state, const float *y, float margin, hipStream_t stream);
+
 /* Radiance estimate L = f_r tau / N per channel (f_r = 1/pi), in the caller's original kernel order.
  * out_rgb[3]: device arrays of n floats. */
 int hk_read_radiance(hk_ctx *ctx, int set_id, const void *state, float *const out_rgb[3], hipStream_t stream);

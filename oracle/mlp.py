@@ -14,7 +14,7 @@ What it defines (the GPU library must reproduce it):
   to bfloat16 exactly where the GPU rounds them (``emulate=True``), or in plain float64
   (``emulate=False``, for finite-difference checks);
 * Adam (Kingma and Ba 2015) on float32-rounded master parameters;
-* the proposal: r = clamp(r1 exp(y), lb, r_current).
+* the proposal: r = clamp(r1 exp(y + margin), lb, r_current).
 
 Parameter vector order: W1 (36 x 64, row = input), b1 (64), W2 (64 x 64, row = input), b2 (64),
 w3 (64), b3 (1) -- 6593 values.
@@ -188,7 +188,9 @@ def init_params(seed: int) -> np.ndarray:
     return pack(d).astype(F32).astype(np.float64)
 
 
-def propose(y: np.ndarray, r1: float, lb: float, r_cur: np.ndarray) -> np.ndarray:
-    """Proposed radii: r1 exp(y), clamped to [lb, r_current] (never larger than the current radius)."""
-    r = (np.float64(r1) * np.exp(np.asarray(y, np.float64))).astype(F32)
+def propose(y: np.ndarray, r1: float, lb: float, r_cur: np.ndarray, margin: float = 0.0) -> np.ndarray:
+    """Proposed radii: r1 exp(y + margin) (the sum in float32), clamped to [lb, r_current] (never
+    larger than the current radius)."""
+    e = (np.asarray(y, F32) + F32(margin)).astype(np.float64)
+    r = (np.float64(F32(r1)) * np.exp(e)).astype(F32)
     return np.minimum(np.maximum(r, F32(lb)), np.asarray(r_cur, F32))

@@ -45,6 +45,7 @@ struct SetInfo {
     bool init = false;
     uint64_t gen = 0;          // bumped by every hk_set_kernels (a graph records the generation)
     int64_t H = 0;
+    float r1 = 0.0f;           // the set's initial radius
     int iter = 0;              // completed iterations
     bool has_nrm = false;
     bool J_const = true;       // every J so far equal -> table entries t < iter stay valid
@@ -285,6 +286,7 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, dou
     S.init = true;
     S.gen = ++ctx->gen;
     S.H = n;
+    S.r1 = (float)r1;
     S.has_nrm = has_nrm;
     return HK_OK;
 }
@@ -691,6 +693,180 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
     ctx->p = rc == HK_OK ? best : saved;
     if (rc) return rc;
     if (chosen) *chosen = ctx->p;
+    return HK_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// learned radius proposal
+// ------------------------------------------------------------------------------------------------
+
+extern "C" int hk_mlp_state_bytes(size_t *out)
+{
+    if (!out) return fail(HK_E_INVALID_ARG, "hk_mlp_state_bytes: out is NULL");
+    *out = mlp_layout().total;
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_param_count(void) { return MLP_P; }
+
+extern "C" int hk_mlp_workspace_bytes(int64_t n, size_t *out)
+{
+    if (!out || n < 1) return fail(HK_E_INVALID_ARG, "hk_mlp_workspace_bytes: n >= 1 and out needed");
+    *out = align256(sizeof(float) * (size_t)mlp_grid(n) * MLP_PP) + align256(sizeof(float) * MLP_PP);
+    return HK_OK;
+}
+
+static int check_mlp(hk_ctx *ctx, const void *mlp)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "NULL context");
+    if (!mlp || !aligned(mlp)) return fail(HK_E_INVALID_ARG, "network state must be non-NULL and 256-byte aligned");
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_set_params(hk_ctx *ctx, void *mlp, const float *theta, hipStream_t stream)
+{
+    int rc = check_mlp(ctx, mlp);
+    if (rc) return rc;
+    if (!theta) return fail(HK_E_INVALID_ARG, "theta is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_mlp_set(mlp_view(mlp), theta, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_get_params(hk_ctx *ctx, const void *mlp, float *theta_out, hipStream_t stream)
+{
+    int rc = check_mlp(ctx, mlp);
+    if (rc) return rc;
+    if (!theta_out) return fail(HK_E_INVALID_ARG, "theta_out is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipMemcpyAsync(theta_out, mlp_view(const_cast<void *>(mlp)).theta, sizeof(float) * MLP_P,
+                           hipMemcpyDeviceToDevice, stream));
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_forward(hk_ctx *ctx, const void *mlp, const uint16_t *feat, int64_t n, float *y,
+                              hipStream_t stream)
+{
+    int rc = check_mlp(ctx, mlp);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!feat || !y))) return fail(HK_E_INVALID_ARG, "hk_mlp_forward: bad arrays");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_mlp_forward(mlp_view(const_cast<void *>(mlp)), feat, n, y, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+static int mlp_grad_common(hk_ctx *ctx, const void *mlp, const uint16_t *feat, const float *label, int64_t n,
+                           void *ws, size_t ws_bytes, float **part, float **grad)
+{
+    int rc = check_mlp(ctx, mlp);
+    if (rc) return rc;
+    if (n < 1 || !feat || !label) return fail(HK_E_INVALID_ARG, "need n >= 1 samples with features and labels");
+    if (!ws || !aligned(ws)) return fail(HK_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    rc = hk_mlp_workspace_bytes(n, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) return fail(HK_E_SMALL_BUFFER, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    *part = static_cast<float *>(ws);
+    *grad = reinterpret_cast<float *>(static_cast<char *>(ws) + align256(sizeof(float) * (size_t)mlp_grid(n) * MLP_PP));
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_grad(hk_ctx *ctx, const void *mlp, const uint16_t *feat, const float *label, int64_t n,
+                           float *grad_out, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    float *part, *grad;
+    int rc = mlp_grad_common(ctx, mlp, feat, label, n, ws, ws_bytes, &part, &grad);
+    if (rc) return rc;
+    if (!grad_out) return fail(HK_E_INVALID_ARG, "grad_out is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_mlp_grad(mlp_view(const_cast<void *>(mlp)), feat, label, n, part, grad_out, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_train_step(hk_ctx *ctx, void *mlp, const uint16_t *feat, const float *label, int64_t n, float lr,
+                                 void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    float *part, *grad;
+    int rc = mlp_grad_common(ctx, mlp, feat, label, n, ws, ws_bytes, &part, &grad);
+    if (rc) return rc;
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(HK_E_INVALID_ARG, "lr must be finite and > 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const MlpView M = mlp_view(mlp);
+    launch_mlp_grad(M, feat, label, n, part, grad, stream);
+    launch_mlp_adam(M, grad, lr, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_photons *ph, float it_code,
+                               uint16_t *feat, uint32_t *counts, void *workspace, size_t workspace_bytes,
+                               hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "NULL context");
+    if (set_id < 0 || set_id >= MAX_SETS || !ctx->sets[set_id].init)
+        return fail(HK_E_BAD_STATE, "set %d has no kernels", set_id);
+    if (!state || !aligned(state)) return fail(HK_E_INVALID_ARG, "state must be 256-byte aligned");
+    if (!workspace || !aligned(workspace)) return fail(HK_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (!ph || !feat) return fail(HK_E_INVALID_ARG, "photons and feat are required");
+    const SetInfo &S = ctx->sets[set_id];
+    const hk_photons &P = *ph;
+    if (P.n_stored < 0 || P.n_stored > MAX_STORED) return fail(HK_E_UNSUPPORTED, "n_stored out of range");
+    if (P.n_stored > 0)
+        for (int a = 0; a < 3; ++a)
+            if (!P.pos[a]) return fail(HK_E_INVALID_ARG, "pos is NULL");
+    const bool nrm_test = nrm_test_of(ctx, set_id, P);
+    if (nrm_test && (!P.nrm[1] || !P.nrm[2])) return fail(HK_E_INVALID_ARG, "nrm must be all NULL or all set");
+    const WsLayout W = make_ws_layout(1, &P.n_stored, &S.H);
+    if (workspace_bytes < W.total)
+        return fail(HK_E_SMALL_BUFFER, "workspace of %zu bytes, %zu needed", workspace_bytes, W.total);
+    HIP_TRY(hipSetDevice(ctx->device));
+    char *w = static_cast<char *>(workspace);
+    const StateView st = make_view(state, layout_of(ctx, S.H));
+    launch_plan_fixed(st.hdr, S.r1, W.max_cells[0], stream);
+    GridLaunch g{};
+    g.hdr = st.hdr;
+    for (int a = 0; a < 3; ++a) {
+        g.src.pos[a] = P.pos[a];
+        g.src.nrm[a] = nrm_test ? P.nrm[a] : nullptr;
+        g.src.flux[a] = P.pos[a];          // the payload's flux plane is not read here
+        g.src.mis[a] = nullptr;
+    }
+    g.n = P.n_stored;
+    g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
+    g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
+    g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
+    g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
+    g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
+    g.part = reinterpret_cast<uint32_t *>(w + W.part);
+    g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
+    g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
+    g.pay = reinterpret_cast<float4 *>(w + W.pay);
+    g.pstride = W.n_total;
+    g.ncells_bound = W.max_cells[0];
+    build_grid(g, stream);
+    launch_features(st, S.H, g.cstart, g.pay, g.pstride, nrm_test, ctx->p.normal_cos_min, it_code, feat, counts,
+                    stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+extern "C" int hk_mlp_propose(hk_ctx *ctx, int set_id, void *state, const float *y, float margin,
+                              hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "NULL context");
+    if (set_id < 0 || set_id >= MAX_SETS || !ctx->sets[set_id].init)
+        return fail(HK_E_BAD_STATE, "set %d has no kernels", set_id);
+    if (!state || !aligned(state)) return fail(HK_E_INVALID_ARG, "state must be 256-byte aligned");
+    if (!y) return fail(HK_E_INVALID_ARG, "y is NULL");
+    if (!isfinite(margin)) return fail(HK_E_INVALID_ARG, "margin must be finite");
+    const SetInfo &S = ctx->sets[set_id];
+    if (S.iter >= ctx->p.max_iters) return fail(HK_E_BAD_STATE, "set %d reached max_iters", set_id);
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_propose(make_view(state, layout_of(ctx, S.H)), S.H, y, margin, stream);
+    HIP_TRY(hipGetLastError());
     return HK_OK;
 }
 

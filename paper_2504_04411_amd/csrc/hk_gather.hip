@@ -78,23 +78,6 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (idx << 4));
 }
 
-// Grid cells overlapping [p - r - margin, p + r + margin] on every axis; false if none.
-__device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], float r, int c0[3], int c1[3])
-{
-    const float mg = fmaf(r, 1e-4f, hdr->margin_abs);
-    bool any = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float f0 = floorf((p[a] - r - mg - hdr->dom_lo[a]) * hdr->cell_inv[a]);
-        const float f1 = floorf((p[a] + r + mg - hdr->dom_lo[a]) * hdr->cell_inv[a]);
-        const float dm = (float)(hdr->dims[a] - 1);
-        any = any && (f0 <= f1) && (f1 >= 0.0f) && (f0 <= dm);
-        c0[a] = (int)fminf(fmaxf(f0, 0.0f), dm);
-        c1[a] = (int)fminf(fmaxf(f1, 0.0f), dm);
-    }
-    return any;
-}
-
 constexpr int UNROLL = 4;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 

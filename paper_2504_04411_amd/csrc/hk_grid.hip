@@ -245,6 +245,43 @@ __global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cel
     for (int b = 0; b < RHIST_BINS; ++b) hdr->rhist[b] = 0;
 }
 
+// One thread: a grid of fixed cell size `cell` (grown until the cell count fits max_cells) over the
+// set's domain, without advancing the iteration (used to count light vertices around the kernels
+// outside an iteration).
+__global__ void plan_fixed_kernel(SetHeader *hdr, float cell, uint32_t max_cells)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float ext[3], emax = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        ext[a] = hdr->dom_hi[a] - hdr->dom_lo[a];
+        emax = fmaxf(emax, ext[a]);
+    }
+    if (!(cell > 0.0f)) cell = emax;
+    int dims[3];
+    for (int guard = 0; guard < 200; ++guard) {
+        double tot = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            float q = floorf(ext[a] / cell);
+            int d = (q < 1.0f || hdr->kflat[a]) ? 1 : (q > 65535.0f ? 65535 : (int)q);
+            dims[a] = d;
+            tot *= d;
+        }
+        if (tot <= (double)max_cells) break;
+        cell *= 1.25f;
+    }
+    for (int a = 0; a < 3; ++a) {
+        hdr->dims[a] = dims[a];
+        hdr->cell_inv[a] = (float)dims[a] / ext[a];
+    }
+    hdr->ncells = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2];
+    hdr->cell = cell;
+}
+
+void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream_t s)
+{
+    plan_fixed_kernel<<<1, 64, 0, s>>>(hdr, cell, max_cells);
+}
+
 __device__ __forceinline__ uint32_t cell_key(const SetHeader *hdr, float x, float y, float z)
 {
     const float p[3] = {x, y, z};

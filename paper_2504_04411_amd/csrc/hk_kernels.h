@@ -65,6 +65,69 @@ struct BatchArgs {
     int lanes_light, lanes_heavy;
 };
 
+// Learned radius proposal: 36 -> 64 -> 64 -> 1 perceptron. Parameter vector: W1 (36 x 64, row =
+// input), b1, W2 (64 x 64, row = input), b2, w3, b3.
+constexpr int MLP_IN = 36, MLP_INP = 64, MLP_H = 64;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = MLP_IN * MLP_H, MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_H * MLP_H, MLP_OFF_W3 = MLP_OFF_B2 + MLP_H, MLP_OFF_B3 = MLP_OFF_W3 + MLP_H;
+constexpr int MLP_P = MLP_OFF_B3 + 1;              // 6593 parameters
+constexpr int MLP_PP = 6656;                       // parameters + squared error, rounded up
+constexpr int MLP_MAX_WG = 1024;                   // workgroups of a gradient launch
+
+// Device view of a network's state: float32 master parameters, Adam moments (float64), bfloat16
+// copies of the weights as the matrix cores read them (W1 padded to 64 input rows), step count.
+struct MlpView {
+    float *theta;
+    double *m, *v;
+    uint16_t *w1b, *w2b, *w3b;
+    int64_t *step;
+};
+
+struct MlpLayout {
+    size_t theta = 0, m = 0, v = 0, w1b = 0, w2b = 0, w3b = 0, step = 0, total = 0;
+};
+
+inline MlpLayout mlp_layout()
+{
+    MlpLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.theta = take(sizeof(float) * MLP_PP);
+    L.m = take(sizeof(double) * MLP_PP);
+    L.v = take(sizeof(double) * MLP_PP);
+    L.w1b = take(2 * MLP_INP * MLP_H);
+    L.w2b = take(2 * MLP_H * MLP_H);
+    L.w3b = take(2 * MLP_H);
+    L.step = take(sizeof(int64_t));
+    L.total = off;
+    return L;
+}
+
+inline MlpView mlp_view(void *base)
+{
+    char *b = static_cast<char *>(base);
+    const MlpLayout L = mlp_layout();
+    MlpView M;
+    M.theta = reinterpret_cast<float *>(b + L.theta);
+    M.m = reinterpret_cast<double *>(b + L.m);
+    M.v = reinterpret_cast<double *>(b + L.v);
+    M.w1b = reinterpret_cast<uint16_t *>(b + L.w1b);
+    M.w2b = reinterpret_cast<uint16_t *>(b + L.w2b);
+    M.w3b = reinterpret_cast<uint16_t *>(b + L.w3b);
+    M.step = reinterpret_cast<int64_t *>(b + L.step);
+    return M;
+}
+
+int mlp_grid(int64_t n);
+void launch_mlp_set(const MlpView &M, const float *theta, hipStream_t s);
+void launch_mlp_forward(const MlpView &M, const uint16_t *feat, int64_t n, float *y, hipStream_t s);
+void launch_mlp_grad(const MlpView &M, const uint16_t *feat, const float *label, int64_t n, float *part, float *grad,
+                     hipStream_t s);
+void launch_mlp_adam(const MlpView &M, const float *grad, float lr, hipStream_t s);
+void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, const float4 *pay, int64_t pstride,
+                     bool nrm_test, float cos_min, float it_code, uint16_t *feat, uint32_t *counts, hipStream_t s);
+void launch_propose(const StateView &st, int64_t H, const float *y, float margin, hipStream_t s);
+
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
                 uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres);
 void build_grid(const GridLaunch &g, hipStream_t s);
@@ -72,6 +135,7 @@ void init_set(const InitLaunch &g, hipStream_t s);
 void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s);
 void launch_plan(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile, uint32_t max_cells,
                  hipStream_t s);
+void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream_t s);
 void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all, double alpha_f,
                   hipStream_t s);
 void launch_cost(const ListLaunch &l, hipStream_t s);

@@ -90,6 +90,17 @@ def lib():
             "hk_f_quantile": ([c.c_double, c.c_double, c.c_double], c.c_double),
             "hk_profile_enable": ([_vp, c.c_int], c.c_int),
             "hk_profile_read": ([_vp, c.POINTER(c.c_double), c.c_int], c.c_int),
+            "hk_mlp_param_count": ([], c.c_int),
+            "hk_mlp_state_bytes": ([c.POINTER(c.c_size_t)], c.c_int),
+            "hk_mlp_workspace_bytes": ([c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
+            "hk_mlp_set_params": ([_vp, _vp, _vp, _vp], c.c_int),
+            "hk_mlp_get_params": ([_vp, _vp, _vp, _vp], c.c_int),
+            "hk_mlp_forward": ([_vp, _vp, _vp, c.c_int64, _vp, _vp], c.c_int),
+            "hk_mlp_grad": ([_vp, _vp, _vp, _vp, c.c_int64, _vp, _vp, c.c_size_t, _vp], c.c_int),
+            "hk_mlp_train_step": ([_vp, _vp, _vp, _vp, c.c_int64, c.c_float, _vp, c.c_size_t, _vp], c.c_int),
+            "hk_mlp_features": ([_vp, c.c_int, _vp, c.POINTER(hk_photons), c.c_float, _vp, _vp, _vp, c.c_size_t, _vp],
+                                c.c_int),
+            "hk_mlp_propose": ([_vp, c.c_int, _vp, _vp, c.c_float, _vp], c.c_int),
             "hk_version": ([], c.c_int),
             "hk_last_error": ([], c.c_char_p),
         }
@@ -275,6 +286,51 @@ def hk_profile_read(ctx):
     out = (ctypes.c_double * 6)()
     check(lib().hk_profile_read(ctx, out, 6))
     return list(out)
+
+
+def hk_mlp_param_count() -> int:
+    return lib().hk_mlp_param_count()
+
+
+def hk_mlp_state_bytes() -> int:
+    out = ctypes.c_size_t()
+    check(lib().hk_mlp_state_bytes(ctypes.byref(out)))
+    return out.value
+
+
+def hk_mlp_workspace_bytes(n: int) -> int:
+    out = ctypes.c_size_t()
+    check(lib().hk_mlp_workspace_bytes(int(n), ctypes.byref(out)))
+    return out.value
+
+
+def hk_mlp_set_params(ctx, mlp, theta, stream):
+    check(lib().hk_mlp_set_params(ctx, mlp, theta, stream))
+
+
+def hk_mlp_get_params(ctx, mlp, theta_out, stream):
+    check(lib().hk_mlp_get_params(ctx, mlp, theta_out, stream))
+
+
+def hk_mlp_forward(ctx, mlp, feat, n, y, stream):
+    check(lib().hk_mlp_forward(ctx, mlp, feat, int(n), y, stream))
+
+
+def hk_mlp_grad(ctx, mlp, feat, label, n, grad_out, ws, ws_bytes, stream):
+    check(lib().hk_mlp_grad(ctx, mlp, feat, label, int(n), grad_out, ws, int(ws_bytes), stream))
+
+
+def hk_mlp_train_step(ctx, mlp, feat, label, n, lr, ws, ws_bytes, stream):
+    check(lib().hk_mlp_train_step(ctx, mlp, feat, label, int(n), float(lr), ws, int(ws_bytes), stream))
+
+
+def hk_mlp_features(ctx, set_id, state, photons, it_code, feat, counts, ws, ws_bytes, stream):
+    check(lib().hk_mlp_features(ctx, int(set_id), state, ctypes.byref(photons), float(it_code), feat, counts, ws,
+                                int(ws_bytes), stream))
+
+
+def hk_mlp_propose(ctx, set_id, state, y, margin, stream):
+    check(lib().hk_mlp_propose(ctx, int(set_id), state, y, float(margin), stream))
 
 
 def hk_version() -> int:

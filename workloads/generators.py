@@ -324,6 +324,25 @@ def config1(seed: int = 1, **kw) -> Workload:
 
 
 # ---------------------------------------------------------------------------------------------
+# Config 3: box scenes with jittered light and occluder (training and held-out scenes of the
+# learned radius proposal)
+# ---------------------------------------------------------------------------------------------
+
+def config3(seed: int, res: int = 512, J: int = 2_000_000, n_iter: int = 64, r1: float = 0.05) -> Workload:
+    """Config 1's box with the light and the occluder centre each moved by U(-0.1, 0.1) per axis
+    (the light's height capped at 0.92, below the ceiling). Seeds 30-33 are the training scenes,
+    seed 39 the held-out one."""
+    meta = rng_for(seed, 0, META_KEY)
+    dl = meta.uniform(-0.1, 0.1, 3)
+    ds = meta.uniform(-0.1, 0.1, 3)
+    light = (float(0.5 + dl[0]), float(min(0.9 + dl[1], 0.92)), float(0.5 + dl[2]))
+    sphere = (float(0.5 + ds[0]), float(0.5 + ds[1]), float(0.5 + ds[2]))
+    w = box_scene(seed=seed, res=res, J=J, n_iter=n_iter, r1=r1, light=light, sphere_c=sphere)
+    w.name = f"box-jittered-{seed}"
+    return w
+
+
+# ---------------------------------------------------------------------------------------------
 # Config 2: many independent sets of uneven size
 # ---------------------------------------------------------------------------------------------
 
