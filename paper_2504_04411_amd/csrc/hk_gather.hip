@@ -9,9 +9,9 @@
 // G partial results are combined in a fixed order (deterministic) and the kernel's epilogue runs.
 //
 // The test and the accumulation are decoupled: each step tests G candidates (one per lane), the
-// in-disk ones are queued in LDS (lane order), and whenever a kernel has G queued photons its G
-// lanes accumulate them together, so the accumulation runs with every lane busy instead of only the
-// third of lanes whose candidate fell inside the disk.
+// in-disk ones are queued in LDS (lane order) and later accumulated G at a time by the kernel's G
+// lanes together, so the accumulation runs with every lane busy instead of only the third of lanes
+// whose candidate fell inside the disk.
 //
 // Light kernels share a wave (8 lanes each by default); kernels whose stencil holds more than
 // `heavy_cost` photons get a whole wave and are listed first, so the longest work starts first. The
@@ -81,13 +81,19 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
 constexpr int UNROLL = 4;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
+constexpr int QCAP = 4;            // queue capacity per kernel, in multiples of its G lanes
+
 struct Lds {
     float4 slot[NG][WAVE];        // lane-private pairs (S, err S, Q, err Q) per group
-    float4 part[2][WAVE];         // lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
-    uint32_t rs[WAVE];            // row start in the payload
-    uint32_t ro[WAVE];            // row offset in the concatenation (exclusive)
-    uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
-    uint32_t queue[2 * WAVE];     // in-disk photons waiting for accumulation, 2 G slots per kernel
+    union {
+        struct {
+            uint32_t rs[WAVE];    // row start in the payload
+            uint32_t ro[WAVE];    // row offset in the concatenation (exclusive)
+            uint32_t re[WAVE];    // row end in the concatenation (inclusive scan)
+            uint32_t queue[QCAP * WAVE];   // in-disk photons waiting for accumulation: a ring of 4 G per kernel
+        };
+        float4 part[2][WAVE];     // after the walk: lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
+    };
 };
 
 // Per-kernel constants of one work item, held in registers by the kernel's G lanes.
@@ -147,26 +153,26 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
     ++c.cnt;
 }
 
-// Each kernel's G lanes take up to G queued photons; the rest move to the front. `head` counts the
-// kernel's photons accumulated so far (mod G): lane j takes the queued photon whose position in the
-// kernel's in-disk stream is congruent to j mod G, so every lane sums a fixed subsequence of the
-// stream whatever the drain times (which depend on the other kernels of the wave), and the result
-// of a kernel does not depend on its neighbours in the launch.
+// Each kernel's queue is a ring of QCAP G entries; `head` counts the kernel's photons accumulated so
+// far. A drain takes G photons from every kernel that has G queued (all the rest when `flush`):
+// lane j takes the photon whose position in the kernel's in-disk stream is congruent to j mod G, so
+// every lane sums a fixed subsequence of the stream whatever the drain times (which depend on the
+// other kernels of the wave), and the result of a kernel does not depend on its neighbours in the
+// launch. Drains are called when some kernel holds (QCAP - 1) G photons, so a step's push (at most
+// G) never overwrites a queued photon, and most kernels then have a full G to drain.
 template <int G, bool NRM, bool VCM>
-__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j, int base, const Query &K,
-                                           float cos_min, const float4 *rA, const float4 *rB, const float4 *rC,
-                                           Lds &L, int lane, Acc &c)
+__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool flush, int j, int base,
+                                           const Query &K, float cos_min, const float4 *rA, const float4 *rB,
+                                           const float4 *rC, Lds &L, int lane, Acc &c)
 {
     __syncthreads();
-    const uint32_t n = min(qlen, (uint32_t)G);
+    const uint32_t n = (qlen >= (uint32_t)G) ? (uint32_t)G : (flush ? qlen : 0u);
     const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
-    if (k < n) accumulate<NRM, VCM>(L.queue[2 * base + k], K, cos_min, rA, rB, rC, L, lane, c);
-    const uint32_t rem = qlen - n;
-    const uint32_t moved = ((uint32_t)j < rem) ? L.queue[2 * base + G + j] : 0u;
-    __syncthreads();
-    if ((uint32_t)j < rem) L.queue[2 * base + j] = moved;
-    qlen = rem;
-    head = (head + n) & (uint32_t)(G - 1);
+    if (k < n)
+        accumulate<NRM, VCM>(L.queue[QCAP * base + ((head + k) & (uint32_t)(QCAP * G - 1))], K, cos_min, rA, rB, rC,
+                             L, lane, c);
+    qlen -= n;
+    head += n;
 }
 
 template <int G, bool NRM, bool VCM>
@@ -290,15 +296,16 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
                 // queue the in-disk photons of this step in lane order
                 const uint64_t m = __ballot(in);
                 const uint32_t before = (uint32_t)__popcll(m & below);
-                if (in) L.queue[2 * base + qlen + before] = pis[u];
+                if (in) L.queue[QCAP * base + ((head + qlen + before) & (uint32_t)(QCAP * G - 1))] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
-                if (__ballot(qlen >= (uint32_t)G) != 0ull)
-                    drain_once<G, NRM, VCM>(qlen, head, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+                if (__ballot(qlen >= (uint32_t)((QCAP - 1) * G)) != 0ull)
+                    drain_once<G, NRM, VCM>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
             }
         }
     }
     while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM>(qlen, head, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+        drain_once<G, NRM, VCM>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+    __syncthreads();                                  // the queue's memory becomes the flux partials
 
     // Combine the G lane partials in lane order. Columns 0..11 are the groups, 12 and 13 the flux
     // pairs; lane j of the kernel combines columns j, j + G, ... (all of them in lane order).
