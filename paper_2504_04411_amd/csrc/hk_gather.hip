@@ -81,19 +81,14 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
 constexpr int UNROLL = 4;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
-constexpr int QCAP = 4;            // queue capacity per kernel, in multiples of its G lanes
+constexpr int QCAP = 3;            // queue capacity per kernel, in multiples of its G lanes
 
+// 13.25 KB per wavefront (12 wavefronts per CU; the register budget allows 12 as well).
 struct Lds {
     float4 slot[NG][WAVE];        // lane-private pairs (S, err S, Q, err Q) per group
-    union {
-        struct {
-            uint32_t rs[WAVE];    // row start in the payload
-            uint32_t ro[WAVE];    // row offset in the concatenation (exclusive)
-            uint32_t re[WAVE];    // row end in the concatenation (inclusive scan)
-            uint32_t queue[QCAP * WAVE];   // in-disk photons waiting for accumulation: a ring of 4 G per kernel
-        };
-        float4 part[2][WAVE];     // after the walk: lane-private flux pairs (R, cR, G, cG), (B, cB, -, -)
-    };
+    uint32_t dl[WAVE];            // row start in the payload minus the row's offset in the concatenation
+    uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
+    uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: a ring of 3 G per kernel
 };
 
 // Per-kernel constants of one work item, held in registers by the kernel's G lanes.
@@ -153,13 +148,20 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
     ++c.cnt;
 }
 
-// Each kernel's queue is a ring of QCAP G entries; `head` counts the kernel's photons accumulated so
-// far. A drain takes G photons from every kernel that has G queued (all the rest when `flush`):
-// lane j takes the photon whose position in the kernel's in-disk stream is congruent to j mod G, so
-// every lane sums a fixed subsequence of the stream whatever the drain times (which depend on the
-// other kernels of the wave), and the result of a kernel does not depend on its neighbours in the
-// launch. Drains are called when some kernel holds (QCAP - 1) G photons, so a step's push (at most
-// G) never overwrites a queued photon, and most kernels then have a full G to drain.
+// Each kernel's queue is a ring of QCAP G entries starting at `head` (mod QCAP G; head mod G also
+// counts the kernel's photons accumulated so far, mod G). A drain takes G photons from every kernel
+// that has G queued (all the rest when `flush`): lane j takes the photon whose position in the
+// kernel's in-disk stream is congruent to j mod G, so every lane sums a fixed subsequence of the
+// stream whatever the drain times (which depend on the other kernels of the wave), and the result
+// of a kernel does not depend on its neighbours in the launch. Drains are called when some kernel
+// holds (QCAP - 1) G photons, so a step's push (at most G) never overwrites a queued photon, and
+// most kernels then have a full G to drain.
+template <int G>
+__device__ __forceinline__ uint32_t ring(uint32_t i)
+{
+    return (i >= (uint32_t)(QCAP * G)) ? i - (uint32_t)(QCAP * G) : i;     // i < 2 QCAP G
+}
+
 template <int G, bool NRM, bool VCM>
 __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool flush, int j, int base,
                                            const Query &K, float cos_min, const float4 *rA, const float4 *rB,
@@ -168,11 +170,9 @@ __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool 
     __syncthreads();
     const uint32_t n = (qlen >= (uint32_t)G) ? (uint32_t)G : (flush ? qlen : 0u);
     const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
-    if (k < n)
-        accumulate<NRM, VCM>(L.queue[QCAP * base + ((head + k) & (uint32_t)(QCAP * G - 1))], K, cos_min, rA, rB, rC,
-                             L, lane, c);
+    if (k < n) accumulate<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k)], K, cos_min, rA, rB, rC, L, lane, c);
     qlen -= n;
-    head += n;
+    head = ring<G>(head + n);
 }
 
 template <int G, bool NRM, bool VCM>
@@ -255,8 +255,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
         const uint32_t inc = group_incl_scan<G>(len, j);
         const uint32_t total = __shfl(inc, base + G - 1, WAVE);
         __syncthreads();
-        L.rs[lane] = st;
-        L.ro[lane] = inc - len;
+        L.dl[lane] = st - (inc - len);
         L.re[lane] = inc;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
@@ -265,7 +264,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
         // the U candidates are tested from registers; those inside the disk are queued.
         int cur = 0;
         uint32_t row_end = L.re[base];
-        uint32_t delta = L.rs[base] - L.ro[base];
+        uint32_t delta = L.dl[base];
         uint32_t vi = (uint32_t)j;
         for (int s0 = 0; s0 < nsteps; s0 += UNROLL) {
             float4 a[UNROLL];
@@ -278,7 +277,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
                     while (vi >= row_end) {
                         ++cur;
                         row_end = L.re[base + cur];
-                        delta = L.rs[base + cur] - L.ro[base + cur];
+                        delta = L.dl[base + cur];
                     }
                     pis[u] = vi + delta;
                     a[u] = ld4(rA, pis[u]);
@@ -296,7 +295,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
                 // queue the in-disk photons of this step in lane order
                 const uint64_t m = __ballot(in);
                 const uint32_t before = (uint32_t)__popcll(m & below);
-                if (in) L.queue[QCAP * base + ((head + qlen + before) & (uint32_t)(QCAP * G - 1))] = pis[u];
+                if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
                 if (__ballot(qlen >= (uint32_t)((QCAP - 1) * G)) != 0ull)
                     drain_once<G, NRM, VCM>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
@@ -305,14 +304,21 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
     }
     while (__ballot(qlen > 0u) != 0ull)
         drain_once<G, NRM, VCM>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
-    __syncthreads();                                  // the queue's memory becomes the flux partials
-
-    // Combine the G lane partials in lane order. Columns 0..11 are the groups, 12 and 13 the flux
-    // pairs; lane j of the kernel combines columns j, j + G, ... (all of them in lane order).
-    L.part[0][lane] = make_float4(c.fR, c.cR, c.fG, c.cG);
-    L.part[1][lane] = make_float4(c.fB, c.cB, 0.0f, 0.0f);
     __syncthreads();
-    constexpr int COLS = NG + 2;
+
+    // Combine the G lane partials in lane order: lane j of the kernel combines groups j, j + G, ...
+    // from LDS; every lane folds the flux pairs of the kernel's lanes from registers.
+    float fR = 0.0f, xR = 0.0f, fG = 0.0f, xG = 0.0f, fB = 0.0f, xB = 0.0f;
+    for (int l = 0; l < G; ++l) {
+        const int src = base + l;
+        acc2(fR, xR, __shfl(c.fR, src, WAVE));
+        xR += __shfl(c.cR, src, WAVE);
+        acc2(fG, xG, __shfl(c.fG, src, WAVE));
+        xG += __shfl(c.cG, src, WAVE);
+        acc2(fB, xB, __shfl(c.fB, src, WAVE));
+        xB += __shfl(c.cB, src, WAVE);
+    }
+    constexpr int COLS = NG;
     constexpr int CPL = (COLS + G - 1) / G;
     float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
 #pragma unroll
@@ -327,7 +333,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
         }
         if (col < COLS) {
             for (int l = 0; l < G; ++l) {
-                const float4 x = (col < NG) ? L.slot[col][base + l] : L.part[col - NG][base + l];
+                const float4 x = L.slot[col][base + l];
                 acc2(S[k], cS[k], x.x);
                 cS[k] += x.y;
                 acc2(Q[k], cQ[k], x.z);
@@ -359,10 +365,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
     }
     const double ssb = group_sum<G>(bl) / m;
     const double ssw = group_sum<G>(wl);
-    constexpr int K12 = NG / G, J12 = NG % G, K13 = (NG + 1) / G, J13 = (NG + 1) % G;
-    const float flR = __shfl(S[K12] + cS[K12], base + J12, WAVE);
-    const float flG = __shfl(Q[K12] + cQ[K12], base + J12, WAVE);
-    const float flB = __shfl(S[K13] + cS[K13], base + J13, WAVE);
+    const float flR = fR + xR, flG = fG + xG, flB = fB + xB;
 
     int shrink = 0;
     if (active && j == 0) {
