@@ -110,13 +110,16 @@ template <bool NRM, bool VCM>
 __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float cos_min, const float4 *rA,
                                            const float4 *rB, const float4 *rC, Lds &L, int lane, Acc &c)
 {
+    // The three loads are issued together; a photon that fails the normal test is then added as
+    // zeros (an exact no-op on the pairs), so no second load round trip waits on the test.
     const float4 a = ld4(rA, pi);
     const float4 f = ld4(rC, pi);
     float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
     if (NRM || VCM) bN = ld4(rB, pi);
+    bool ok = true;
     if (NRM) {
         const float cs = fmaf(K.nv[2], bN.z, fmaf(K.nv[1], bN.y, K.nv[0] * bN.x));
-        if (!(cs >= cos_min)) return;
+        ok = cs >= cos_min;
     }
     const float dx = K.p[0] - a.x, dy = K.p[1] - a.y, dz = K.p[2] - a.z;
     const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
@@ -138,6 +141,7 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
         wG = f.y;
         wB = f.z;
     }
+    if (NRM && !ok) psi = wR = wG = wB = 0.0f;
     float4 sv = L.slot[g][lane];
     acc2(sv.x, sv.y, psi);
     acc2_sq(sv.z, sv.w, psi);
@@ -145,7 +149,7 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
     acc2(c.fR, c.cR, wR);
     acc2(c.fG, c.cG, wG);
     acc2(c.fB, c.cB, wB);
-    ++c.cnt;
+    c.cnt += ok ? 1u : 0u;
 }
 
 // Each kernel's queue is a ring of QCAP G entries starting at `head` (mod QCAP G; head mod G also
