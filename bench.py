@@ -105,6 +105,73 @@ def learned_vs_plain(args, ex):
     return keep
 
 
+def _gen2(args):
+    s, it, J, edge, ca = args
+    from workloads import generators as G
+    return s, it, G.config2_photons(2, s, it, J, edge, ca)
+
+
+def batched_sets(args, ex, n_iter=8):
+    """Config 2 (16 independent planar sets of uneven size) through the batched launch: one
+    hk_iterate call for all sets per iteration, against one call per set, and the batched iteration
+    replayed from a captured graph against the same iteration run eagerly."""
+    import torch
+    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+    from workloads import generators as G
+    meta = G.config2_sets(2)
+    ws = G.config2(seed=2, n_iter=n_iter)
+    n = len(ws)
+    batches = [[None] * n for _ in range(n_iter)]
+    jobs = [(s, it, J, edge, ca) for it in range(n_iter) for s, (_, J, edge, ca) in enumerate(meta)]
+    for s, it, b in ex.map(_gen2, jobs):
+        batches[it][s] = DevicePhotons.upload(b)
+    p = ws[0].params
+    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    ids = list(range(n))
+    H = sum(w.kernels.n for w in ws)
+
+    def reset():
+        for s, w in enumerate(ws):
+            est.set_kernels(s, w.kernels.pos, None, r1=w.params.r1, rmin=w.params.rmin)
+        est._workspace(max(est.workspace_for(bb, ids) for bb in batches))
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    reset()
+    tuning = est.tuning()
+    if not args.no_autotune:
+        for it in range(2):
+            est.iterate(ids, batches[it])
+        tuning = est.autotune(ids, batches[2 % n_iter])
+    out = {"workload": f"16 planar sets (config 2): {H} hit points and "
+                       f"{sum(m[1] for m in meta)} light paths per iteration in all, {n_iter} iterations",
+           "hit_points": H, "iterations": n_iter, "tuning": tuning}
+    t = timed(lambda: [est.iterate(ids, batches[it]) for it in range(n_iter)])
+    out["batched_queries_per_s"] = round(H * n_iter / t, 1)
+    t = timed(lambda: [est.iterate([s], [batches[it][s]]) for it in range(n_iter) for s in ids])
+    out["one_call_per_set_queries_per_s"] = round(H * n_iter / t, 1)
+    t = timed(lambda: [est.iterate(ids, batches[0]) for _ in range(n_iter)])
+    out["eager_repeated_batch_queries_per_s"] = round(H * n_iter / t, 1)
+    reset()
+    g = est.capture(ids, batches[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_iter):
+        g.launch()
+    torch.cuda.synchronize()
+    out["graph_repeated_batch_queries_per_s"] = round(H * n_iter / (time.perf_counter() - t0), 1)
+    g.close()
+    est.close()
+    return out
+
+
 def make_batches(seed, n, J, workers):
     out = [None] * n
     with ProcessPoolExecutor(max_workers=workers) as ex:
@@ -140,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-set (config 2) measurement")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed job, copy a MIB-sized device buffer once (reference for HBM "
@@ -226,6 +294,9 @@ def main():
                          "shrunk_frac": float((radii < np.float32(p.r1)).mean())},
         "roofline": roof,
     }
+    if not args.no_batched:
+        with ProcessPoolExecutor(max_workers=args.workers) as ex:
+            out["batched_sets"] = batched_sets(args, ex)
     if not args.no_learned:
         with ProcessPoolExecutor(max_workers=args.workers) as ex:
             out["learned_vs_plain"] = learned_vs_plain(args, ex)

@@ -78,7 +78,7 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (idx << 4));
 }
 
-constexpr int UNROLL = 4;         // candidate loads in flight per lane
+constexpr int UNROLL = 8;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
 constexpr int QCAP = 3;            // queue capacity per kernel, in multiples of its G lanes

@@ -346,10 +346,9 @@ def config3(seed: int, res: int = 512, J: int = 2_000_000, n_iter: int = 64, r1:
 # Config 2: many independent sets of uneven size
 # ---------------------------------------------------------------------------------------------
 
-def config2(seed: int = 2, n_sets: int = 16, side_range=(64, 1024), J_range=(500_000, 8_000_000),
-            n_iter: int = 16, scale: float = 1.0) -> List[Workload]:
-    """Independent planar sets; side and J log-uniform, r1 = 0.05 * sqrt(1e5 / J) keeps about 785
-    photons per disk. ``scale`` < 1 shrinks every side and J for quick runs."""
+def config2_sets(seed: int = 2, n_sets: int = 16, side_range=(64, 1024), J_range=(500_000, 8_000_000),
+                 scale: float = 1.0):
+    """Per-set (side, J, edge, caustic centre) of config 2, drawn from the seed's meta stream."""
     meta = rng_for(seed, 0, META_KEY)
     lo, hi = np.log(side_range[0]), np.log(side_range[1])
     sides = np.exp(meta.uniform(lo, hi, n_sets))
@@ -360,12 +359,26 @@ def config2(seed: int = 2, n_sets: int = 16, side_range=(64, 1024), J_range=(500
     for s in range(n_sets):
         side = max(4, int(round(sides[s] * math.sqrt(scale))))
         J = max(1000, int(round(Js[s] * scale)))
+        out.append((side, J, float(edges[s]), (float(caus[s, 0]), float(caus[s, 1]))))
+    return out
+
+
+def config2_photons(seed: int, s: int, it: int, J: int, edge: float, ca) -> PhotonBatch:
+    """Light vertices of set s of config 2 at iteration it (every emitted path is stored)."""
+    return _planar_batch(rng_for(seed, s, it), J, J, edge, ca, 0.5)
+
+
+def config2(seed: int = 2, n_sets: int = 16, side_range=(64, 1024), J_range=(500_000, 8_000_000),
+            n_iter: int = 16, scale: float = 1.0) -> List[Workload]:
+    """Independent planar sets; side and J log-uniform, r1 = 0.05 * sqrt(1e5 / J) keeps about 785
+    photons per disk. ``scale`` < 1 shrinks every side and J for quick runs."""
+    out = []
+    for s, (side, J, edge, ca) in enumerate(config2_sets(seed, n_sets, side_range, J_range, scale)):
         r1 = 0.05 * math.sqrt(1e5 / J)
         ks = KernelSet(pos=grid_kernels(side, side))
-        edge, ca = float(edges[s]), (float(caus[s, 0]), float(caus[s, 1]))
 
         def photons(it, s=s, J=J, edge=edge, ca=ca):
-            return _planar_batch(rng_for(seed, s, it), J, J, edge, ca, 0.5)
+            return config2_photons(seed, s, it, J, edge, ca)
 
         out.append(Workload(f"set{s}", Params(r1=r1, n_iter=n_iter), ks, photons, seed, s,
                             info=dict(H=side * side, J=J, edge=edge, caustic=ca)))
