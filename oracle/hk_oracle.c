@@ -10,7 +10,8 @@
  * plain uniform grid (grid mode), and accumulates in float64:
  *   count       number of light vertices inside the disk,
  *   S[g], Q[g]  sum and sum of squares of the test sample of group g (Sec. 3.2.1-3.2.2, Sec. 5.1
- *               step 2), 12 groups = 2 equi-areal annuli x 6 equi-angular sectors (Sec. 6.1.1),
+ *               step 2), 12 groups = 2 equi-areal annuli x 6 equi-angular sectors (Sec. 6.1.1);
+ *               with one test per RGB channel (Sec. 5.1, chromatic light), 3 x 12 sums,
  *   flux[c]     sum of the photon flux (PPM) or of w * throughput (vertex merging).
  *
  * Per-pair decisions (inside the disk, normal consistency, group) and the per-pair test sample are
@@ -88,12 +89,13 @@ typedef struct {
     const float *pdvcm, *pdvm;             /* vertex merging: light partials */
     int vcm;
     float cos_min;
+    int rgb;                               /* 1: one test sample per RGB channel (3 x 12 groups) */
     /* outputs */
     uint32_t *count;
     double *S, *Q, *flux;
 } oracle_args;
 
-/* Per-pair work for kernel h and photon j; returns 1 if the pair is inside the disk. */
+/* Per-pair work for kernel h and photon j (S, Q: the kernel's 12 or, per channel, 3 x 12 sums). */
 static inline void pair(const oracle_args *A, int64_t h, int64_t j, float r2, float inv_eta, float wc,
                         uint32_t *cnt, double *S, double *Q, double *fl)
 {
@@ -130,6 +132,28 @@ static inline void pair(const oracle_args *A, int64_t h, int64_t j, float r2, fl
         fl[2] += (double)(w * B);
     }
     *cnt += 1;
+    if (A->rgb) {
+        /* one test per channel (Sec. 5.1: chromatic light): the channel itself replaces the
+         * luminance, weighted as the luminance would be in vertex merging */
+        float pc[3];
+        if (!A->vcm) {
+            pc[0] = R;
+            pc[1] = G;
+            pc[2] = B;
+        } else {
+            const float p_dir = 0.31830988618379067f;
+            float wl = fmaf(A->pdvm[j], p_dir, A->pdvcm[j] * inv_eta);
+            float w = 1.0f / ((1.0f + wl) + wc);
+            pc[0] = w * (A->cbR[h] * R);
+            pc[1] = w * (A->cbG[h] * G);
+            pc[2] = w * (A->cbB[h] * B);
+        }
+        for (int c = 0; c < 3; ++c) {
+            S[c * NG + g] += (double)pc[c];
+            Q[c * NG + g] += (double)pc[c] * (double)pc[c];
+        }
+        return;
+    }
     S[g] += (double)psi;
     Q[g] += (double)psi * (double)psi;
 }
@@ -149,11 +173,14 @@ static void kernel_consts(const oracle_args *A, int64_t h, float *r2, float *inv
     }
 }
 
+static int64_t sq_width(const oracle_args *A) { return A->rgb ? 3 * NG : NG; }
+
 static void zero_out(const oracle_args *A, int64_t h)
 {
+    const int64_t w = sq_width(A);
     A->count[h] = 0;
-    memset(A->S + h * NG, 0, NG * sizeof(double));
-    memset(A->Q + h * NG, 0, NG * sizeof(double));
+    memset(A->S + h * w, 0, (size_t)w * sizeof(double));
+    memset(A->Q + h * w, 0, (size_t)w * sizeof(double));
     memset(A->flux + h * 3, 0, 3 * sizeof(double));
 }
 
@@ -169,7 +196,8 @@ int oracle_gather_allpairs(const oracle_args *A, int nthreads)
         kernel_consts(A, h, &r2, &inv_eta, &wc);
         zero_out(A, h);
         for (int64_t j = 0; j < A->J; ++j)
-            pair(A, h, j, r2, inv_eta, wc, A->count + h, A->S + h * NG, A->Q + h * NG, A->flux + h * 3);
+            pair(A, h, j, r2, inv_eta, wc, A->count + h, A->S + h * sq_width(A), A->Q + h * sq_width(A),
+                 A->flux + h * 3);
     }
     return 0;
 }
@@ -243,8 +271,8 @@ int oracle_gather_grid(const oracle_args *A, int nthreads)
                 for (int64_t cx = c0[0]; cx <= c1[0]; ++cx) {
                     int64_t c = (cz * dim[1] + cy) * dim[0] + cx;
                     for (int64_t q = start[c]; q < start[c + 1]; ++q)
-                        pair(A, h, order[q], r2, inv_eta, wc, A->count + h, A->S + h * NG, A->Q + h * NG,
-                             A->flux + h * 3);
+                        pair(A, h, order[q], r2, inv_eta, wc, A->count + h, A->S + h * sq_width(A),
+                             A->Q + h * sq_width(A), A->flux + h * 3);
                 }
     }
     free(start);

@@ -64,6 +64,7 @@ class _Args(ctypes.Structure):
         ("pdvcm", _P), ("pdvm", _P),
         ("vcm", ctypes.c_int),
         ("cos_min", ctypes.c_float),
+        ("rgb", ctypes.c_int),
         ("count", ctypes.POINTER(ctypes.c_uint32)),
         ("S", ctypes.POINTER(ctypes.c_double)), ("Q", ctypes.POINTER(ctypes.c_double)),
         ("flux", ctypes.POINTER(ctypes.c_double)),
@@ -121,13 +122,13 @@ def group_of(yu: float, yv: float, d2: float, r2: float) -> int:
 @dataclass
 class GatherResult:
     count: np.ndarray      # (H,) uint32
-    S: np.ndarray          # (H, 12) float64
-    Q: np.ndarray          # (H, 12) float64
+    S: np.ndarray          # (H, 12) float64; (H, 36) with one test per channel (R groups, G, B)
+    Q: np.ndarray          # like S
     flux: np.ndarray       # (H, 3) float64
 
 
 def gather(kernels, photons, r: np.ndarray, vcm: bool = False, use_grid: bool = True, cos_min: float = 0.5,
-           idx: Optional[np.ndarray] = None, nthreads: int = 0) -> GatherResult:
+           idx: Optional[np.ndarray] = None, nthreads: int = 0, rgb: bool = False) -> GatherResult:
     """Per-kernel sums of one iteration for the kernels ``idx`` (all when None) at radii ``r``."""
     sel = np.arange(kernels.n) if idx is None else np.asarray(idx)
     H = sel.size
@@ -144,7 +145,8 @@ def gather(kernels, photons, r: np.ndarray, vcm: bool = False, use_grid: bool = 
     cb = _rows(kernels.cam_beta[:, sel]) if vcm else [None] * 3
     cm = _rows(kernels.cam_mis[:, sel]) if vcm else [None] * 3
     pm = _rows(photons.mis) if vcm else [None] * 3
-    out = GatherResult(np.zeros(H, np.uint32), np.zeros((H, NG)), np.zeros((H, NG)), np.zeros((H, 3)))
+    w = 3 * NG if rgb else NG
+    out = GatherResult(np.zeros(H, np.uint32), np.zeros((H, w)), np.zeros((H, w)), np.zeros((H, 3)))
     a = _Args()
     a.H = H
     a.kx, a.ky, a.kz = map(_fp, kp)
@@ -162,6 +164,7 @@ def gather(kernels, photons, r: np.ndarray, vcm: bool = False, use_grid: bool = 
     a.pdvcm, a.pdvm = _fp(pm[0]), _fp(pm[2])
     a.vcm = 1 if vcm else 0
     a.cos_min = F32(cos_min)
+    a.rgb = 1 if rgb else 0
     a.count = out.count.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
     a.S = out.S.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     a.Q = out.Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -254,12 +257,14 @@ class OracleState:
     Fc: Optional[np.ndarray] = None
     shrink: Optional[np.ndarray] = None
     m: Optional[np.ndarray] = None
+    F_channels: Optional[np.ndarray] = None   # (H, 3) per-channel F with one test per channel
 
 
-def init_state(H: int, r1: float, r_init: Optional[np.ndarray] = None) -> OracleState:
+def init_state(H: int, r1: float, r_init: Optional[np.ndarray] = None, rgb: bool = False) -> OracleState:
     r = np.full(H, F32(r1), dtype=F32) if r_init is None else np.asarray(r_init, dtype=F32).copy()
+    w = 3 * NG if rgb else NG
     return OracleState(r=r, t=np.zeros(H, np.int64), nseen=np.zeros(H, np.int64),
-                       S=np.zeros((H, NG)), Q=np.zeros((H, NG)), tau=np.zeros((H, 3)))
+                       S=np.zeros((H, w)), Q=np.zeros((H, w)), tau=np.zeros((H, 3)))
 
 
 def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nthreads: int = 0,
@@ -269,9 +274,10 @@ def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nt
     ``fcrit_override`` (callable m -> F_c) replaces the quantile, for forced-decision tests.
     """
     vcm = params.mode == "vcm"
+    rgb = getattr(params, "stats", "luma") == "rgb"
     H = kernels.n
     g = gathered if gathered is not None else gather(kernels, photons, st.r, vcm=vcm, use_grid=use_grid,
-                                                      nthreads=nthreads)
+                                                      nthreads=nthreads, rgb=rgb)
     i = st.iters + 1                                  # 1-based global iteration index
     J = int(photons.J)
     st.J_hist.append(J)
@@ -283,12 +289,25 @@ def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nt
     # m = sum of J over the kept iterations; zero samples included (one sample per light sub-path)
     cumJ = np.concatenate([[0], np.cumsum(st.J_hist[::-1])]).astype(np.float64)
     m = cumJ[st.t]
-    F = f_statistic(st.S, st.Q, m)
-    ssw = within_ss(st.S, st.Q, m)
     Fc = fcrit_override(m) if fcrit_override is not None else f_critical(m, params.alpha_f, NG)
-    valid = (st.nseen > 0) & (ssw > 0) & (m >= 2)
+    Fch = None
+    if not rgb:
+        F = f_statistic(st.S, st.Q, m)
+        ssw = within_ss(st.S, st.Q, m)
+        valid = (st.nseen > 0) & (ssw > 0) & (m >= 2)
+        shrink = valid & (F > Fc)                      # NaN compares false: keep
+    else:
+        # one test per channel (Sec. 5.1, chromatic light): reject when any channel rejects; the
+        # reported F is the largest channel F (NaN channels ignored)
+        Fch = np.stack([f_statistic(st.S[:, c * NG:(c + 1) * NG], st.Q[:, c * NG:(c + 1) * NG], m)
+                        for c in range(3)], 1)
+        sswc = np.stack([within_ss(st.S[:, c * NG:(c + 1) * NG], st.Q[:, c * NG:(c + 1) * NG], m)
+                         for c in range(3)], 1)
+        col = lambda x: np.asarray(x)[..., None] if np.ndim(x) else x  # noqa: E731
+        validc = (st.nseen[:, None] > 0) & (sswc > 0) & col(m >= 2)
+        shrink = np.any(validc & (Fch > col(Fc)), axis=1)
+        F = np.fmax.reduce(Fch, axis=1)
     F = np.where(st.nseen > 0, F, np.nan)
-    shrink = valid & (F > Fc)                          # NaN compares false: keep
     # progressive estimate: each iteration with its own radius r_i (Eq. progressive-VCM-estimator)
     r64 = st.r.astype(np.float64)
     norm = 1.0 / (J * math.pi * r64 * r64)
@@ -306,6 +325,7 @@ def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nt
     st.nseen[shrink] = 0
     st.iters = i
     st.count, st.F, st.Fc, st.shrink, st.m = g.count, F, np.broadcast_to(Fc, F.shape).copy(), shrink, m
+    st.F_channels = Fch
     return st
 
 

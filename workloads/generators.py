@@ -30,6 +30,7 @@ class Params:
     n_s: int = 6              # equi-angular sectors per annulus
     mode: str = "ppm"         # "ppm" or "vcm"
     n_iter: int = 16
+    stats: str = "luma"       # test sample: "luma" (luminance) or "rgb" (one test per channel)
 
     def __post_init__(self):
         if self.rmin is None:
