@@ -54,7 +54,9 @@ extern "C" {
 #define HK_MODE_PPM 0           /* progressive photon mapping: sample = luminance of the photon flux */
 #define HK_MODE_VCM 1           /* vertex merging of VCM+: sample = MIS-weighted luminance of the path */
 
-/* test channels (Sec. 5.1 end: luminance by default, one test per RGB channel for chromatic light) */
+/* test channels (Sec. 5.1 end: luminance by default, one test per RGB channel for chromatic light:
+ * the three channels' F are tested against the same critical value and the radius shrinks when any
+ * channel rejects; the reported F is the largest channel F) */
 #define HK_STATS_LUMA 0
 #define HK_STATS_RGB 1
 
@@ -233,7 +235,8 @@ int hk_read_radii(hk_ctx *ctx, int set_id, const void *state, float *out, hipStr
 int hk_read_debug(hk_ctx *ctx, int set_id, const void *state, uint32_t *count, double *F, double *Fc,
                   uint8_t *decision, uint32_t *t, hipStream_t stream);
 
-/* Retained group sums in float64 (device, n x 12 each, row-major, original order): S and Q as the
+/* Retained group sums in float64 (device, row-major, original order): S and Q, n x 12 each with the
+ * luminance test and n x 36 with one test per channel (column = channel * 12 + group), as the
  * compensated float32 pairs (value + collected rounding errors), and the estimate tau (n x 3). */
 int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *S, double *Q, double *tau,
                  hipStream_t stream);

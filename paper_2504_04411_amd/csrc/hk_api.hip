@@ -142,7 +142,8 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
         return fail(HK_E_INVALID_ARG, "rmin must be in [0, r1]");
     if (p->n_a != 2 || p->n_s != 6) return fail(HK_E_UNSUPPORTED, "only n_a = 2, n_s = 6 is implemented");
     if (p->mode != HK_MODE_PPM && p->mode != HK_MODE_VCM) return fail(HK_E_INVALID_ARG, "unknown mode");
-    if (p->stats_channel != HK_STATS_LUMA) return fail(HK_E_UNSUPPORTED, "only the luminance test is implemented");
+    if (p->stats_channel != HK_STATS_LUMA && p->stats_channel != HK_STATS_RGB)
+        return fail(HK_E_INVALID_ARG, "stats_channel must be HK_STATS_LUMA or HK_STATS_RGB");
     if (!(p->normal_cos_min >= -1.0f && p->normal_cos_min <= 1.0f))
         return fail(HK_E_INVALID_ARG, "normal_cos_min must be in [-1, 1]");
     if (p->max_iters < 1 || p->max_iters > 65536) return fail(HK_E_INVALID_ARG, "max_iters must be in [1, 65536]");
@@ -196,7 +197,9 @@ extern "C" int hk_set_tuning(hk_ctx *ctx, float cell_scale, int heavy_cost, int 
     return HK_OK;
 }
 
-static Layout layout_of(const hk_ctx *ctx, int64_t H) { return make_layout(H, ctx->p.max_iters); }
+static int channels(const hk_ctx *ctx) { return ctx->p.stats_channel == HK_STATS_RGB ? 3 : 1; }
+
+static Layout layout_of(const hk_ctx *ctx, int64_t H) { return make_layout(H, ctx->p.max_iters, channels(ctx)); }
 
 extern "C" int hk_state_bytes(hk_ctx *ctx, int64_t n_kernels, size_t *out)
 {
@@ -538,7 +541,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         a.lanes_light = p.lanes_light;
         a.lanes_heavy = p.lanes_heavy;
         if (pe) HIP_TRY(hipEventRecord(pe->e[3], stream));
-        launch_gather(a, W.h_total, nrm_test, vcm, stream);
+        launch_gather(a, W.h_total, nrm_test, vcm, channels(ctx), stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[4], stream));
         launch_tally(table, ids, W.h_total, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[5], stream));
@@ -914,9 +917,10 @@ __global__ void read_sums_kernel(StateView st, int64_t n, double *S, double *Q, 
     const uint32_t j = st.orig[s];
     const size_t a = st.astride;
     const float *sq = st.sq0 + s, *tv = st.tau0 + s;
-    for (int g = 0; g < NG; ++g) {
-        if (S) S[(int64_t)j * NG + g] = (double)sq[(4 * g) * a] + (double)sq[(4 * g + 1) * a];
-        if (Q) Q[(int64_t)j * NG + g] = (double)sq[(4 * g + 2) * a] + (double)sq[(4 * g + 3) * a];
+    const int w = NG * st.nch;                  // columns: channel * NG + group
+    for (int g = 0; g < w; ++g) {
+        if (S) S[(int64_t)j * w + g] = (double)sq[(4 * g) * a] + (double)sq[(4 * g + 1) * a];
+        if (Q) Q[(int64_t)j * w + g] = (double)sq[(4 * g + 2) * a] + (double)sq[(4 * g + 3) * a];
     }
     if (tau)
         for (int c = 0; c < 3; ++c) tau[(int64_t)j * 3 + c] = (double)tv[(2 * c) * a] + (double)tv[(2 * c + 1) * a];

@@ -83,9 +83,11 @@ constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
 constexpr int QCAP = 3;            // queue capacity per kernel, in multiples of its G lanes
 
-// 13.25 KB per wavefront (12 wavefronts per CU; the register budget allows 12 as well).
+// 13.25 KB per wavefront with one test channel (12 wavefronts per CU; the register budget allows
+// 12 as well); 37.25 KB with one test per RGB channel.
+template <int CH>
 struct Lds {
-    float4 slot[NG][WAVE];        // lane-private pairs (S, err S, Q, err Q) per group
+    float4 slot[NG * CH][WAVE];   // lane-private pairs (S, err S, Q, err Q) per channel and group
     uint32_t dl[WAVE];            // row start in the payload minus the row's offset in the concatenation
     uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
     uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: a ring of 3 G per kernel
@@ -106,9 +108,9 @@ struct Acc {
 // Adds the photon pi (already inside the disk) to this lane's group sums and flux sum when it
 // passes the normal-consistency test. The distance vector is recomputed from the payload with the
 // same float32 operations as in the test, so the values are those the test saw.
-template <bool NRM, bool VCM>
+template <bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float cos_min, const float4 *rA,
-                                           const float4 *rB, const float4 *rC, Lds &L, int lane, Acc &c)
+                                           const float4 *rB, const float4 *rC, Lds<CH> &L, int lane, Acc &c)
 {
     // The three loads are issued together; a photon that fails the normal test is then added as
     // zeros (an exact no-op on the pairs), so no second load round trip waits on the test.
@@ -126,7 +128,8 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
     const float yu = fmaf(dz, K.u[2], fmaf(dy, K.u[1], dx * K.u[0]));
     const float yv = fmaf(dz, K.v[2], fmaf(dy, K.v[1], dx * K.v[0]));
     const int g = group_of(yu, yv, d2, K.r2);
-    float psi, wR, wG, wB;
+    // psi: the luminance test sample; pR, pG, pB: the per-channel samples; wR, wG, wB: the flux
+    float psi, wR, wG, wB, pR, pG, pB;
     if (VCM) {
         const float wl = fmaf(bN.w, INV_PI_F, f.w * K.inv_eta);
         const float w = 1.0f / ((1.0f + wl) + K.wc);
@@ -135,17 +138,32 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
         wR = w * f.x;
         wG = w * f.y;
         wB = w * f.z;
+        pR = w * (K.cb[0] * f.x);
+        pG = w * (K.cb[1] * f.y);
+        pB = w * (K.cb[2] * f.z);
     } else {
         psi = a.w;
-        wR = f.x;
-        wG = f.y;
-        wB = f.z;
+        wR = pR = f.x;
+        wG = pG = f.y;
+        wB = pB = f.z;
     }
-    if (NRM && !ok) psi = wR = wG = wB = 0.0f;
-    float4 sv = L.slot[g][lane];
-    acc2(sv.x, sv.y, psi);
-    acc2_sq(sv.z, sv.w, psi);
-    L.slot[g][lane] = sv;
+    if (NRM && !ok) psi = wR = wG = wB = pR = pG = pB = 0.0f;
+    if (CH == 1) {
+        float4 sv = L.slot[g][lane];
+        acc2(sv.x, sv.y, psi);
+        acc2_sq(sv.z, sv.w, psi);
+        L.slot[g][lane] = sv;
+    } else {
+        // one test per channel (chromatic light): the channel's sample replaces the luminance
+        const float pc[3] = {pR, pG, pB};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float4 sv = L.slot[ch * NG + g][lane];
+            acc2(sv.x, sv.y, pc[ch]);
+            acc2_sq(sv.z, sv.w, pc[ch]);
+            L.slot[ch * NG + g][lane] = sv;
+        }
+    }
     acc2(c.fR, c.cR, wR);
     acc2(c.fG, c.cG, wG);
     acc2(c.fB, c.cB, wB);
@@ -166,21 +184,22 @@ __device__ __forceinline__ uint32_t ring(uint32_t i)
     return (i >= (uint32_t)(QCAP * G)) ? i - (uint32_t)(QCAP * G) : i;     // i < 2 QCAP G
 }
 
-template <int G, bool NRM, bool VCM>
+template <int G, bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool flush, int j, int base,
                                            const Query &K, float cos_min, const float4 *rA, const float4 *rB,
-                                           const float4 *rC, Lds &L, int lane, Acc &c)
+                                           const float4 *rC, Lds<CH> &L, int lane, Acc &c)
 {
     __syncthreads();
     const uint32_t n = (qlen >= (uint32_t)G) ? (uint32_t)G : (flush ? qlen : 0u);
     const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
-    if (k < n) accumulate<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k)], K, cos_min, rA, rB, rC, L, lane, c);
+    if (k < n)
+        accumulate<NRM, VCM, CH>(L.queue[QCAP * base + ring<G>(head + k)], K, cos_min, rA, rB, rC, L, lane, c);
     qlen -= n;
     head = ring<G>(head + n);
 }
 
-template <int G, bool NRM, bool VCM>
-__device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t entry, bool active)
+template <int G, bool NRM, bool VCM, int CH>
+__device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t entry, bool active)
 {
     const int lane = threadIdx.x;
     const int j = lane % G;
@@ -235,7 +254,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
         K.cb[2] = fslot(SL_CB + 2)[q];
     }
 #pragma unroll
-    for (int g = 0; g < NG; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int g = 0; g < NG * CH; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
     uint32_t qlen = 0, head = 0;
 
@@ -302,12 +321,12 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
                 if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
                 if (__ballot(qlen >= (uint32_t)((QCAP - 1) * G)) != 0ull)
-                    drain_once<G, NRM, VCM>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+                    drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
             }
         }
     }
     while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
     __syncthreads();
 
     // Combine the G lane partials in lane order: lane j of the kernel combines groups j, j + G, ...
@@ -322,14 +341,14 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
         acc2(fB, xB, __shfl(c.fB, src, WAVE));
         xB += __shfl(c.cB, src, WAVE);
     }
-    constexpr int COLS = NG;
+    constexpr int COLS = NG * CH;                 // column = channel * NG + group
     constexpr int CPL = (COLS + G - 1) / G;
     float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
         S[k] = cS[k] = Q[k] = cQ[k] = 0.0f;
-        if (active && col < NG) {
+        if (active && col < COLS) {
             S[k] = fslot(SL_SQ + 4 * col)[q];
             cS[k] = fslot(SL_SQ + 4 * col + 1)[q];
             Q[k] = fslot(SL_SQ + 4 * col + 2)[q];
@@ -348,35 +367,54 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
     const uint32_t cnt_q = group_sum_u<G>(c.cnt);
     const uint32_t t_new = active ? uslot(SL_T)[q] + 1u : 1u;
     const double m = active ? mprefix[iter] - mprefix[iter - (int)t_new] : 2.0;
+    // per channel: total, between- and within-group sums of squares (Eq. f-statistic), the lane's
+    // columns first, then summed over the kernel's lanes
     double sg[CPL], qg[CPL];
-    double tl = 0.0;
+    double tl[CH], bl[CH], wl[CH], ssb[CH], ssw[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) tl[ch] = bl[ch] = wl[ch] = 0.0;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
-        const bool grp = j + k * G < NG;
+        const int col = j + k * G;
+        const bool grp = col < COLS;
         sg[k] = grp ? (double)S[k] + (double)cS[k] : 0.0;
         qg[k] = grp ? (double)Q[k] + (double)cQ[k] : 0.0;
-        tl += sg[k];
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) tl[ch] += (grp && col / NG == ch) ? sg[k] : 0.0;
     }
-    const double tot = group_sum<G>(tl);
-    double bl = 0.0, wl = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) tl[ch] = group_sum<G>(tl[ch]);
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
-        if (j + k * G < NG) {
-            const double d = sg[k] - tot / NG;
-            bl += d * d;
-            wl += qg[k] - sg[k] * sg[k] / m;
+        const int col = j + k * G;
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            if (col < COLS && col / NG == ch) {
+                const double d = sg[k] - tl[ch] / NG;
+                bl[ch] += d * d;
+                wl[ch] += qg[k] - sg[k] * sg[k] / m;
+            }
         }
     }
-    const double ssb = group_sum<G>(bl) / m;
-    const double ssw = group_sum<G>(wl);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        ssb[ch] = group_sum<G>(bl[ch]) / m;
+        ssw[ch] = group_sum<G>(wl[ch]);
+    }
     const float flR = fR + xR, flG = fG + xG, flB = fB + xB;
 
     int shrink = 0;
     if (active && j == 0) {
         const uint32_t seen = uslot(SL_NSEEN)[q] + cnt_q;
-        const double F = (ssb / (NG - 1)) / (ssw / (NG * (m - 1.0)));
         const double Fc = fctab[t_new];
-        shrink = (seen > 0u && ssw > 0.0 && m >= 2.0 && (F > Fc)) ? 1 : 0;
+        // one test per channel: reject when any channel rejects; report the largest F
+        double F = (double)NAN;
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch) {
+            const double Fch = (ssb[ch] / (NG - 1)) / (ssw[ch] / (NG * (m - 1.0)));
+            if (seen > 0u && ssw[ch] > 0.0 && m >= 2.0 && Fch > Fc) shrink = 1;
+            F = fmax(F, Fch);
+        }
         // this iteration's kernel estimate with its own radius
         const float denom = Jf * (PI_F * K.r2);
         float eR = flR / denom, eG = flG / denom, eB = flB / denom;
@@ -406,7 +444,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
-        if (active && col < NG) {
+        if (active && col < COLS) {
             fslot(SL_SQ + 4 * col)[q] = shrink ? 0.0f : S[k];
             fslot(SL_SQ + 4 * col + 1)[q] = shrink ? 0.0f : cS[k];
             fslot(SL_SQ + 4 * col + 2)[q] = shrink ? 0.0f : Q[k];
@@ -416,10 +454,10 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds &L, uint32_t ent
     __syncthreads();
 }
 
-template <bool NRM, bool VCM, int GL, int GH>
+template <bool NRM, bool VCM, int CH, int GL, int GH>
 __global__ __launch_bounds__(WAVE) void gather_update_kernel(BatchArgs A)
 {
-    __shared__ Lds L;
+    __shared__ Lds<CH> L;
     const int lane = threadIdx.x;
     constexpr uint32_t KPW_L = WAVE / GL;     // light kernels per wave
     constexpr uint32_t KPW_H = WAVE / GH;     // heavy kernels per wave
@@ -437,19 +475,19 @@ __global__ __launch_bounds__(WAVE) void gather_update_kernel(BatchArgs A)
         if (item < items_h) {
             const uint32_t hi = item * KPW_H + (uint32_t)(lane / GH);
             const bool act = hi < n_heavy;
-            process<GH, NRM, VCM>(A, L, act ? A.heavy[hi] : 0u, act);
+            process<GH, NRM, VCM, CH>(A, L, act ? A.heavy[hi] : 0u, act);
         } else {
             const uint32_t li = (item - items_h) * KPW_L + (uint32_t)(lane / GL);
             const bool act = li < n_light;
-            process<GL, NRM, VCM>(A, L, act ? A.light[li] : 0u, act);
+            process<GL, NRM, VCM, CH>(A, L, act ? A.light[li] : 0u, act);
         }
     }
 }
 
-template <bool NRM, bool VCM>
+template <bool NRM, bool VCM, int CH>
 static void launch_lanes(const BatchArgs &a, int gl, int gh, int grid, hipStream_t s)
 {
-#define HK_LAUNCH(GLV, GHV) gather_update_kernel<NRM, VCM, GLV, GHV><<<grid, WAVE, 0, s>>>(a)
+#define HK_LAUNCH(GLV, GHV) gather_update_kernel<NRM, VCM, CH, GLV, GHV><<<grid, WAVE, 0, s>>>(a)
     if (gh == 16) {
         if (gl == 4) HK_LAUNCH(4, 16);
         else if (gl == 8) HK_LAUNCH(8, 16);
@@ -462,21 +500,30 @@ static void launch_lanes(const BatchArgs &a, int gl, int gh, int grid, hipStream
 #undef HK_LAUNCH
 }
 
-void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, hipStream_t s)
+template <int CH>
+static void launch_modes(const BatchArgs &a, bool nrm, bool vcm, int gl, int gh, int grid, hipStream_t s)
+{
+    if (nrm && vcm)
+        launch_lanes<true, true, CH>(a, gl, gh, grid, s);
+    else if (nrm)
+        launch_lanes<true, false, CH>(a, gl, gh, grid, s);
+    else if (vcm)
+        launch_lanes<false, true, CH>(a, gl, gh, grid, s);
+    else
+        launch_lanes<false, false, CH>(a, gl, gh, grid, s);
+}
+
+void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s)
 {
     if (h_total <= 0) return;
     const int gl = (a.lanes_light == 4 || a.lanes_light == 8) ? a.lanes_light : 16;
     const int gh = (a.lanes_heavy == 16) ? 16 : 64;
     const int64_t per = 8 * (int64_t)XCD_CHUNK;
     const int grid = (int)(cdiv(cdiv(h_total, WAVE / gl), per) * per);
-    if (nrm && vcm)
-        launch_lanes<true, true>(a, gl, gh, grid, s);
-    else if (nrm)
-        launch_lanes<true, false>(a, gl, gh, grid, s);
-    else if (vcm)
-        launch_lanes<false, true>(a, gl, gh, grid, s);
+    if (nch == 3)
+        launch_modes<3>(a, nrm, vcm, gl, gh, grid, s);
     else
-        launch_lanes<false, false>(a, gl, gh, grid, s);
+        launch_modes<1>(a, nrm, vcm, gl, gh, grid, s);
 }
 
 // ------------------------------------------------------------------------------------------------

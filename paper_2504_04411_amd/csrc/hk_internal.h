@@ -50,11 +50,14 @@ struct SetHeader {
 
 // Per-kernel arrays of a set's state, by slot: every slot is `stride` bytes (256-byte aligned, one
 // float or uint32 per kernel); float64 arrays take two slots.
+// The group sums come last: NSQ slots per test channel (1, or 3 with one test per RGB channel).
 enum Slot : int {
     SL_POS = 0, SL_NRM = 3, SL_U = 6, SL_V = 9, SL_R = 12, SL_T = 13, SL_NSEEN = 14, SL_ORIG = 15, SL_CNT = 16,
-    SL_DEC = 17, SL_SQ = 18, SL_TAU = SL_SQ + NSQ, SL_F = SL_TAU + 6, SL_FC = SL_F + 2, SL_CB = SL_FC + 2,
-    SL_CDVCM = SL_CB + 3, SL_CDVM = SL_CDVCM + 1, SL_COUNT = SL_CDVM + 1
+    SL_DEC = 17, SL_TAU = 18, SL_F = SL_TAU + 6, SL_FC = SL_F + 2, SL_CB = SL_FC + 2, SL_CDVCM = SL_CB + 3,
+    SL_CDVM = SL_CDVCM + 1, SL_SQ = SL_CDVM + 1
 };
+
+constexpr int slot_count(int nch) { return SL_SQ + NSQ * nch; }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -63,15 +66,17 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     int64_t H = 0;
     int max_iters = 0;
+    int nch = 1;                    // test channels
     size_t hdr = 0, mprefix = 0, fctab = 0, lbtab = 0, arr = 0, stride = 0, total = 0;
     size_t slot(int k) const { return arr + (size_t)k * stride; }
 };
 
-inline Layout make_layout(int64_t H, int max_iters)
+inline Layout make_layout(int64_t H, int max_iters, int nch)
 {
     Layout L;
     L.H = H;
     L.max_iters = max_iters;
+    L.nch = nch;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.hdr = take(sizeof(SetHeader));
@@ -80,7 +85,7 @@ inline Layout make_layout(int64_t H, int max_iters)
     L.lbtab = take(sizeof(float) * (max_iters + 2));
     L.stride = align256(sizeof(float) * (size_t)H);
     L.arr = off;
-    L.total = L.arr + (size_t)SL_COUNT * L.stride;
+    L.total = L.arr + (size_t)slot_count(nch) * L.stride;
     return L;
 }
 
@@ -93,7 +98,8 @@ struct StateView {
     float *pos[3], *nrm[3], *u[3], *v[3];
     float *r;
     uint32_t *t, *nseen, *orig, *cnt, *dec;
-    float *sq0;          // group sums: array k at sq0 + k * astride
+    float *sq0;          // group sums: array k at sq0 + k * astride, NSQ * nch arrays
+    int nch;             // test channels
     float *tau0;         // estimate: array c at tau0 + c * astride
     uint32_t astride;    // floats between slots
     double *F, *Fc;
@@ -124,6 +130,7 @@ inline StateView make_view(void *base, const Layout &L)
     s.cnt = u(SL_CNT);
     s.dec = u(SL_DEC);
     s.sq0 = f(SL_SQ);
+    s.nch = L.nch;
     s.tau0 = f(SL_TAU);
     s.astride = (uint32_t)(L.stride / sizeof(float));
     s.F = reinterpret_cast<double *>(b + L.slot(SL_F));

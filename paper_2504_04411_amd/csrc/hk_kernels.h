@@ -142,7 +142,7 @@ void launch_cost(const ListLaunch &l, hipStream_t s);
 void launch_split(uint32_t *flag, uint32_t *offs, uint32_t *ids, int64_t n, uint32_t *part, uint32_t *heavy,
                   uint32_t *light, uint32_t *counts, hipStream_t s);
 void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   // bytes: multiple of 4
-void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, hipStream_t s);
+void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
 void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s);
 
 }  // namespace hk

@@ -54,7 +54,7 @@ class DevicePhotons:
 class Estimator:
     """One libhk context with any number of hit-point sets on one GPU."""
 
-    def __init__(self, r1: float, mode: str = "ppm", device: str = "cuda", **overrides):
+    def __init__(self, r1: float, mode: str = "ppm", device: str = "cuda", stats: str = "luma", **overrides):
         dev = torch.device(device)
         if dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -62,6 +62,8 @@ class Estimator:
         torch.cuda.set_device(self.device)
         p = hk.hk_default_params(r1)
         p.mode = hk.HK_MODE_VCM if mode == "vcm" else hk.HK_MODE_PPM
+        p.stats_channel = hk.HK_STATS_RGB if stats == "rgb" else hk.HK_STATS_LUMA
+        self.nch = 3 if stats == "rgb" else 1
         for k, v in overrides.items():
             if v is not None:
                 setattr(p, k, v)
@@ -170,8 +172,8 @@ class Estimator:
 
     def sums(self, set_id: int):
         n = self.n[set_id]
-        S = torch.empty((n, 12), dtype=torch.float64, device=self.device)
-        Q = torch.empty((n, 12), dtype=torch.float64, device=self.device)
+        S = torch.empty((n, 12 * self.nch), dtype=torch.float64, device=self.device)
+        Q = torch.empty((n, 12 * self.nch), dtype=torch.float64, device=self.device)
         tau = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         hk.hk_read_sums(self.ctx, set_id, self.states[set_id].data_ptr(), S.data_ptr(), Q.data_ptr(), tau.data_ptr(),
                         self.stream)

@@ -76,7 +76,7 @@ class Tracker:
         ks = w.kernels
         self.idx = np.arange(ks.n) if idx is None else np.asarray(idx)
         self.oks = sub_kernels(ks, self.idx)
-        self.ost = O.init_state(self.idx.size, self.p.r1)
+        self.ost = O.init_state(self.idx.size, self.p.r1, rgb=self.p.stats == "rgb")
         self.alive = np.ones(self.idx.size, bool)
         self.rep = ParityReport(kernels=self.idx.size)
         self.name = name or w.name
@@ -94,6 +94,8 @@ class Tracker:
         assert bad.size == 0, (f"[{self.name}] iteration {it + 1}: count mismatch at {idx[bad[:5]]}: "
                                f"{cnt[bad[:5]]} vs {ost.count[bad[:5]]}")
         band = np.abs(ost.F - ost.Fc) < BAND
+        if ost.F_channels is not None:             # one test per channel: any channel in the band
+            band = np.any(np.abs(ost.F_channels - ost.Fc[:, None]) < BAND, axis=1)
         dg = d["decision"].astype(bool)
         diff = alive & (dg != ost.shrink)
         assert not np.any(diff & ~band), \
@@ -141,7 +143,7 @@ class Tracker:
 
 def make_estimator(w: G.Workload, **est_kw) -> Estimator:
     p = w.params
-    return Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin, **est_kw)
+    return Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin, stats=p.stats, **est_kw)
 
 
 def run_parity(w: G.Workload, n_iter: int, idx=None, photons_fn=None, est_kw=None, verbose=True) -> ParityReport:
