@@ -34,7 +34,7 @@ OPS_PER_PAIR = 35.0 + 8.0 * 2.9
 # Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane per clock
 # (packed-FP32 and FMA doubling excluded; this build disables packed FP32).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 
 
 def profiled_traffic(kname):
@@ -172,6 +172,58 @@ def batched_sets(args, ex, n_iter=8):
     return out
 
 
+def generated_end_to_end(args, w, tuning):
+    """The box workload with its light vertices generated on the device: every iteration is one
+    replay of a graph that writes the batch (hk_emit_box) and runs the estimator on it. The
+    generation kernel alone is timed with HIP events on the stream it runs on; it writes 36 bytes
+    per slot (position, normal, flux) and reads nothing but its arguments."""
+    import torch
+    from paper_2504_04411_amd import hk
+    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+    p = w.params
+    sc = w.info["scene"]
+    power = float(np.float32(4.0 * math.pi * sc.intensity))
+    scene = hk.box_scene(sc.light, sc.sphere_c, sc.sphere_r, power)
+    J, K, H = args.photons, args.steps, w.kernels.n
+    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    est.set_tuning(tuning["cell_scale"], tuning["heavy_cost"], tuning["lanes_light"], tuning["lanes_heavy"])
+    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)
+    mk = lambda: torch.empty((3, J), dtype=torch.float32, device="cuda")  # noqa: E731
+    buf = DevicePhotons(J=J, pos=mk(), flux=mk(), nrm=mk())
+    est._workspace(est.workspace_for([buf], [0]))
+    est.emit_box(0, scene, args.seed, J, out=buf)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        est.emit_box(0, scene, args.seed, J, out=buf)
+    e1.record()
+    torch.cuda.synchronize()
+    emit_ms = e0.elapsed_time(e1) / K
+    g = est.capture_box([0], [scene], [args.seed], [buf])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    truth = sc.irradiance(w.kernels.pos, w.kernels.nrm) / math.pi
+    L = est.radiance(0).cpu().numpy()
+    mse = float(((L - truth[None, :]) ** 2).mean())
+    g.close()
+    est.close()
+    gbps = 36.0 * J / (emit_ms * 1e-3) / 1e9
+    return {"workload": f"box scene, {args.res}x{args.res} hit points, {J} light sub-paths generated on the "
+                        f"device per iteration (Philox4x32-10, seed {args.seed}), {K} iterations, one graph "
+                        f"replay per iteration",
+            "queries_per_s": round(H * K / dt, 1), "ms_per_iteration": round(dt / K * 1e3, 4),
+            "final_mse_vs_analytic": mse,
+            "emit": {"kernel": "emit_box_kernel", "avg_launch_ms": round(emit_ms, 4),
+                     "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                  "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                                  "work_model": "36 bytes written per slot"}}}
+
+
 def make_batches(seed, n, J, workers):
     out = [None] * n
     with ProcessPoolExecutor(max_workers=workers) as ex:
@@ -208,6 +260,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-set (config 2) measurement")
+    ap.add_argument("--no-generated", action="store_true",
+                    help="skip the run with light vertices generated on the device")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed job, copy a MIB-sized device buffer once (reference for HBM "
@@ -294,6 +348,8 @@ def main():
                          "shrunk_frac": float((radii < np.float32(p.r1)).mean())},
         "roofline": roof,
     }
+    if not args.no_generated:
+        out["generated_end_to_end"] = generated_end_to_end(args, w, tuning)
     if not args.no_batched:
         with ProcessPoolExecutor(max_workers=args.workers) as ex:
             out["batched_sets"] = batched_sets(args, ex)

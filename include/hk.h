@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define HK_VERSION 110
+#define HK_VERSION 120
 
 /* status codes */
 #define HK_OK 0
@@ -162,6 +162,43 @@ int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photon
                     void *workspace, size_t workspace_bytes, hk_graph **out);
 int hk_graph_launch(hk_graph *g, hipStream_t stream);
 int hk_graph_destroy(hk_graph *g);
+
+/* ---- light-vertex generation for the box scene (the light pass before the estimator, Sec. 4) ----
+ * Scene: the unit box [0,1]^3 without its z = 1 wall, an isotropic point light strictly inside it
+ * and an opaque sphere. Light sub-path j of iteration i of set s draws Philox4x32-10 blocks (Salmon
+ * et al., SC 2011) with counter (j, i, s, b) and key (seed mod 2^32, seed div 2^32), b = 0..7; a word
+ * x gives u = (x >> 8) 2^-24. Block b holds the direction attempts 2b (words 0, 1) and 2b + 1 (words
+ * 2, 3): a = 2u - 1, c = 2u' - 1, q = a a + c c, the first attempt with 0 < q < 1 gives the unit
+ * direction (a f, c f, 1 - 2q), f = 2 sqrt(1 - q) (Marsaglia 1972). The vertex is the first wall hit
+ * (per-axis exit distances, the smallest on the first of x, y, z that attains it); the sub-path
+ * leaves no vertex when it escapes through the open top, when the sphere's near intersection lies
+ * in (0, t), or when all 16 attempts fail. Every float32 operation is one correctly rounded IEEE
+ * operation, in the order stated, so the output is bit-reproducible by any implementation of this
+ * definition. */
+typedef struct hk_box_scene {
+    float light[3];        /* point light, each coordinate in (0, 1) */
+    float sphere_c[3];     /* occluder centre (finite) */
+    float sphere_r;        /* occluder radius, >= 0 (0: no occluder) */
+    float power;           /* flux per channel carried by every vertex, e.g. 4 pi I for intensity I */
+} hk_box_scene;
+
+/* Writes the J slots of set `set_id`'s next iteration (its index is read on the device from `state`,
+ * the set's hk_set_kernels state) into pos, nrm and flux (device, J floats each, structure of arrays).
+ * A slot with a vertex holds its position (the hit coordinate exactly 0 or 1), the wall's inward unit
+ * normal and `power` in R, G and B; a slot without one holds NaN positions, a zero normal and zero
+ * flux, which the estimator never gathers. The batch for hk_iterate is then {J_emitted = J,
+ * n_stored = J, pos, nrm, flux}. J in [0, 2^27 - 1]. Asynchronous on `stream`; nothing advances. */
+int hk_emit_box(hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *scene, uint64_t seed,
+                int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3], hipStream_t stream);
+
+/* hk_graph_create with the generation of every set's batch in front: each launch of the graph
+ * writes the batches ph[s] (device arrays; they must be writable, with n_stored == J_emitted and
+ * the normal arrays given) with hk_emit_box's definition for scenes[s] and seeds[s] and the set's
+ * current iteration, then runs the iteration on them. One replay is one complete iteration with no
+ * host work beyond the launch. */
+int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_box_scene *scenes,
+                        const uint64_t *seeds, const hk_photons *ph, void *const *state, void *workspace,
+                        size_t workspace_bytes, hk_graph **out);
 
 /* Times one iteration of the given sets for each of 27 settings (cell_scale 0.7 / 1 / 1.4 x
  * lanes_light 4 / 8 / 16 x heavy_cost 1024 / 4096 / 16384) and keeps the fastest in the context

@@ -567,21 +567,20 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
 // graphs: one iteration of a fixed list of sets captured once, replayed per iteration
 // ------------------------------------------------------------------------------------------------
 
-extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
-                               void *workspace, size_t workspace_bytes, hk_graph **out)
+// Captures [light-vertex generation of every set, when `emit` is given] + one iteration.
+static int graph_capture(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                         void *workspace, size_t workspace_bytes, const EmitLaunch *emit, hk_graph **out)
 {
-    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_graph_create: NULL argument");
-    *out = nullptr;
-    int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
-    if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
-    rc = ensure_streams(ctx);
+    int rc = ensure_streams(ctx);
     if (rc) return rc;
     hk_graph *g = new (std::nothrow) hk_graph();
     if (!g) return fail(HK_E_INVALID_ARG, "out of host memory");
     g->ctx = ctx;
     HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    if (emit)
+        for (int s = 0; s < n_sets; ++s) launch_emit_box(emit[s], ctx->cap);
     rc = enqueue(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, ctx->cap, false, nullptr, &g->all);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
@@ -604,6 +603,104 @@ extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, cons
     }
     *out = g;
     return HK_OK;
+}
+
+extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                               void *workspace, size_t workspace_bytes, hk_graph **out)
+{
+    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_graph_create: NULL argument");
+    *out = nullptr;
+    const int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
+    if (rc) return rc;
+    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, nullptr, out);
+}
+
+// ------------------------------------------------------------------------------------------------
+// light-vertex generation for the box scene
+// ------------------------------------------------------------------------------------------------
+
+static int emit_args(const hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *sc, uint64_t seed,
+                     int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3], EmitLaunch *e)
+{
+    if (set_id < 0 || set_id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", set_id);
+    const SetInfo &S = ctx->sets[set_id];
+    if (!S.init) return fail(HK_E_BAD_STATE, "set %d has no kernels (call hk_set_kernels)", set_id);
+    if (!state || !aligned(state)) return fail(HK_E_INVALID_ARG, "state must be non-NULL and 256-byte aligned");
+    if (!sc) return fail(HK_E_INVALID_ARG, "scene is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (!(sc->light[a] > 0.0f && sc->light[a] < 1.0f))
+            return fail(HK_E_INVALID_ARG, "the light must lie strictly inside the unit box");
+        if (!isfinite(sc->sphere_c[a])) return fail(HK_E_INVALID_ARG, "sphere centre must be finite");
+    }
+    if (!(sc->sphere_r >= 0.0f && isfinite(sc->sphere_r))) return fail(HK_E_INVALID_ARG, "sphere radius must be >= 0");
+    if (!isfinite(sc->power)) return fail(HK_E_INVALID_ARG, "power must be finite");
+    if (J < 0 || J > MAX_STORED) return fail(HK_E_INVALID_ARG, "J must be in [0, 2^27 - 1]");
+    if (J > 0) {
+        if (!pos || !nrm || !flux) return fail(HK_E_INVALID_ARG, "output arrays are NULL");
+        for (int a = 0; a < 3; ++a)
+            if (!pos[a] || !nrm[a] || !flux[a]) return fail(HK_E_INVALID_ARG, "output arrays are NULL");
+    }
+    const Layout L = layout_of(ctx, S.H);
+    *e = EmitLaunch{};
+    e->hdr = reinterpret_cast<const SetHeader *>(static_cast<const char *>(state) + L.hdr);
+    for (int a = 0; a < 3; ++a) {
+        e->L[a] = sc->light[a];
+        e->C[a] = sc->sphere_c[a];
+        if (J > 0) {
+            e->pos[a] = pos[a];
+            e->nrm[a] = nrm[a];
+            e->flux[a] = flux[a];
+        }
+    }
+    e->R = sc->sphere_r;
+    e->power = sc->power;
+    e->key0 = (uint32_t)seed;
+    e->key1 = (uint32_t)(seed >> 32);
+    e->set_id = (uint32_t)set_id;
+    e->J = J;
+    return HK_OK;
+}
+
+extern "C" int hk_emit_box(hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *scene, uint64_t seed,
+                           int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3],
+                           hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_emit_box: NULL context");
+    EmitLaunch e;
+    const int rc = emit_args(ctx, set_id, state, scene, seed, J, pos, nrm, flux, &e);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_emit_box(e, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
+extern "C" int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_box_scene *scenes,
+                                   const uint64_t *seeds, const hk_photons *ph, void *const *state, void *workspace,
+                                   size_t workspace_bytes, hk_graph **out)
+{
+    if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_graph_create_box: NULL argument");
+    *out = nullptr;
+    int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
+    if (rc) return rc;
+    if (!scenes || !seeds) return fail(HK_E_INVALID_ARG, "scenes or seeds is NULL");
+    std::vector<EmitLaunch> em(n_sets);
+    for (int s = 0; s < n_sets; ++s) {
+        const hk_photons &P = ph[s];
+        if ((uint64_t)P.n_stored != P.J_emitted)
+            return fail(HK_E_INVALID_ARG, "set %d: generated batches store every slot (n_stored == J_emitted)", set_ids[s]);
+        if (!P.nrm[0] || !P.nrm[1] || !P.nrm[2])
+            return fail(HK_E_INVALID_ARG, "set %d: generated batches need the normal arrays", set_ids[s]);
+        float *pos[3], *nrm[3], *flux[3];
+        for (int a = 0; a < 3; ++a) {
+            pos[a] = const_cast<float *>(P.pos[a]);
+            nrm[a] = const_cast<float *>(P.nrm[a]);
+            flux[a] = const_cast<float *>(P.flux[a]);
+        }
+        rc = emit_args(ctx, set_ids[s], state[s], &scenes[s], seeds[s], P.n_stored, pos, nrm, flux, &em[s]);
+        if (rc) return rc;
+    }
+    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, em.data(), out);
 }
 
 extern "C" int hk_graph_launch(hk_graph *g, hipStream_t stream)

@@ -145,4 +145,14 @@ void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   /
 void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
 void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s);
 
+// light-vertex generation for the box scene (one thread per slot)
+struct EmitLaunch {
+    const SetHeader *hdr;    // the set's header: its iteration count picks the random stream
+    float L[3], C[3], R, power;
+    uint32_t key0, key1, set_id;
+    int64_t J;
+    float *pos[3], *nrm[3], *flux[3];
+};
+void launch_emit_box(const EmitLaunch &e, hipStream_t s);
+
 }  // namespace hk

@@ -46,6 +46,11 @@ class hk_photons(ctypes.Structure):
     ]
 
 
+class hk_box_scene(ctypes.Structure):
+    _fields_ = [("light", ctypes.c_float * 3), ("sphere_c", ctypes.c_float * 3), ("sphere_r", ctypes.c_float),
+                ("power", ctypes.c_float)]
+
+
 class HKError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libhk error {code}: {msg}")
@@ -74,6 +79,11 @@ def lib():
             "hk_set_tuning": ([_vp, c.c_float, c.c_int, c.c_int, c.c_int], c.c_int),
             "hk_graph_create": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp,
                                  c.c_size_t, c.POINTER(_vp)], c.c_int),
+            "hk_graph_create_box": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_box_scene),
+                                     c.POINTER(c.c_uint64), c.POINTER(hk_photons), c.POINTER(_vp), _vp, c.c_size_t,
+                                     c.POINTER(_vp)], c.c_int),
+            "hk_emit_box": ([_vp, c.c_int, _vp, c.POINTER(hk_box_scene), c.c_uint64, c.c_int64, _vp * 3, _vp * 3,
+                             _vp * 3, _vp], c.c_int),
             "hk_graph_launch": ([_vp, _vp], c.c_int),
             "hk_graph_destroy": ([_vp], c.c_int),
             "hk_autotune": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp),
@@ -235,6 +245,30 @@ def hk_graph_create(ctx, set_ids, photons, states, workspace, workspace_bytes) -
     n, ids, phs, sts = _set_arrays(set_ids, photons, states)
     g = _vp()
     check(lib().hk_graph_create(ctx, n, ids, phs, sts, workspace, int(workspace_bytes), ctypes.byref(g)))
+    return g.value
+
+
+def box_scene(light, sphere_c, sphere_r, power) -> hk_box_scene:
+    sc = hk_box_scene()
+    sc.light[:] = [float(v) for v in light]
+    sc.sphere_c[:] = [float(v) for v in sphere_c]
+    sc.sphere_r = float(sphere_r)
+    sc.power = float(power)
+    return sc
+
+
+def hk_emit_box(ctx, set_id, state, scene: hk_box_scene, seed, J, pos, nrm, flux, stream):
+    check(lib().hk_emit_box(ctx, int(set_id), state, ctypes.byref(scene), int(seed), int(J), _arr3(pos), _arr3(nrm),
+                            _arr3(flux), stream))
+
+
+def hk_graph_create_box(ctx, set_ids, scenes, seeds, photons, states, workspace, workspace_bytes) -> int:
+    n, ids, phs, sts = _set_arrays(set_ids, photons, states)
+    scs = (hk_box_scene * n)(*scenes)
+    sds = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    g = _vp()
+    check(lib().hk_graph_create_box(ctx, n, ids, scs, sds, phs, sts, workspace, int(workspace_bytes),
+                                    ctypes.byref(g)))
     return g.value
 
 
