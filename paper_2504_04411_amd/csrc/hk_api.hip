@@ -747,8 +747,9 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
             return fail(HK_E_INVALID_ARG, "scratch of set %d must be a separate 256-byte aligned buffer", set_ids[s]);
     HIP_TRY(hipSetDevice(ctx->device));
     static const float cells[] = {0.7f, 1.0f, 1.4f};
+    constexpr int n_trials = 3 * 3 * 4;
     static const int lanes[] = {4, 8, 16};
-    static const int heavies[] = {1024, 4096, 16384};
+    static const int heavies[] = {1024, 2048, 4096, 16384};
     const hk_params saved = ctx->p;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -764,12 +765,12 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
         return HK_OK;
     };
     // the first trial (the current settings) also warms up code and caches; it is timed again last
-    for (int trial = -1; trial < 27 && rc == HK_OK; ++trial) {
+    for (int trial = -1; trial < n_trials && rc == HK_OK; ++trial) {
         hk_params q = saved;
         if (trial >= 0) {
-            q.cell_scale = cells[trial / 9];
-            q.lanes_light = lanes[(trial / 3) % 3];
-            q.heavy_cost = heavies[trial % 3];
+            q.cell_scale = cells[trial / 12];
+            q.lanes_light = lanes[(trial / 4) % 3];
+            q.heavy_cost = heavies[trial % 4];
         }
         ctx->p = q;
         rc = copy_states();

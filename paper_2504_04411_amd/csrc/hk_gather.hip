@@ -63,6 +63,21 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// Butterfly sum of the G lanes' compensated pairs (s, c): every step adds the partner's pair with an
+// exact TwoSum, whose error term does not depend on the order of the operands, so both partners
+// hold the same pair and the result does not depend on anything outside the kernel's lanes.
+template <int G>
+__device__ __forceinline__ void group_sum_pair(float &s, float &c)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const float s2 = __shfl_xor(s, o, G);
+        const float c2 = __shfl_xor(c, o, G);
+        c = c + c2;
+        acc2(s, c, s2);
+    }
+}
+
 template <int G>
 __device__ __forceinline__ uint32_t group_sum_u(uint32_t v)
 {
@@ -81,7 +96,8 @@ __device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
 constexpr int UNROLL = 8;         // candidate loads in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
-constexpr int QCAP = 3;            // queue capacity per kernel, in multiples of its G lanes
+constexpr int DRAIN = 2;           // photons per lane per drain (their loads are issued together)
+constexpr int QCAP = DRAIN + 1;    // queue capacity per kernel, in multiples of its G lanes
 
 // 13.25 KB per wavefront with one test channel (12 wavefronts per CU; the register budget allows
 // 12 as well); 37.25 KB with one test per RGB channel.
@@ -105,19 +121,32 @@ struct Acc {
     uint32_t cnt;
 };
 
-// Adds the photon pi (already inside the disk) to this lane's group sums and flux sum when it
-// passes the normal-consistency test. The distance vector is recomputed from the payload with the
-// same float32 operations as in the test, so the values are those the test saw.
-template <bool NRM, bool VCM, int CH>
-__device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float cos_min, const float4 *rA,
-                                           const float4 *rB, const float4 *rC, Lds<CH> &L, int lane, Acc &c)
+// The payload of one queued photon: position and luminance, normal and dVM, flux and dVCM.
+struct Cand {
+    float4 a, b, f;
+};
+
+template <bool NRM, bool VCM>
+__device__ __forceinline__ Cand load_cand(uint32_t pi, const float4 *rA, const float4 *rB, const float4 *rC)
 {
-    // The three loads are issued together; a photon that fails the normal test is then added as
-    // zeros (an exact no-op on the pairs), so no second load round trip waits on the test.
-    const float4 a = ld4(rA, pi);
-    const float4 f = ld4(rC, pi);
-    float4 bN = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-    if (NRM || VCM) bN = ld4(rB, pi);
+    Cand P;
+    P.a = ld4(rA, pi);
+    P.f = ld4(rC, pi);
+    P.b = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+    if (NRM || VCM) P.b = ld4(rB, pi);
+    return P;
+}
+
+// Adds a queued photon (already inside the disk) to this lane's group sums and flux sum when it
+// passes the normal-consistency test. The distance vector is recomputed from the payload with the
+// same float32 operations as in the test, so the values are those the test saw. A photon that
+// fails the normal test is added as zeros (an exact no-op on the pairs), so its loads never wait on
+// the test.
+template <bool NRM, bool VCM, int CH>
+__device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float cos_min, Lds<CH> &L, int lane,
+                                           Acc &c)
+{
+    const float4 a = P.a, f = P.f, bN = P.b;
     bool ok = true;
     if (NRM) {
         const float cs = fmaf(K.nv[2], bN.z, fmaf(K.nv[1], bN.y, K.nv[0] * bN.x));
@@ -171,13 +200,14 @@ __device__ __forceinline__ void accumulate(uint32_t pi, const Query &K, float co
 }
 
 // Each kernel's queue is a ring of QCAP G entries starting at `head` (mod QCAP G; head mod G also
-// counts the kernel's photons accumulated so far, mod G). A drain takes G photons from every kernel
-// that has G queued (all the rest when `flush`): lane j takes the photon whose position in the
-// kernel's in-disk stream is congruent to j mod G, so every lane sums a fixed subsequence of the
-// stream whatever the drain times (which depend on the other kernels of the wave), and the result
-// of a kernel does not depend on its neighbours in the launch. Drains are called when some kernel
-// holds (QCAP - 1) G photons, so a step's push (at most G) never overwrites a queued photon, and
-// most kernels then have a full G to drain.
+// counts the kernel's photons accumulated so far, mod G). A drain takes from every kernel the
+// largest multiple of G up to DRAIN G that it holds (everything up to DRAIN G when `flush`): lane j
+// takes the photons whose positions in the kernel's in-disk stream are congruent to j mod G, in
+// stream order, so every lane sums a fixed subsequence of the stream whatever the drain times
+// (which depend on the other kernels of the wave), and the result of a kernel does not depend on
+// its neighbours in the launch. The loads of a lane's photons are issued together, then the
+// photons are added in order. Drains are called when some kernel holds DRAIN G photons; afterwards
+// every kernel holds fewer than G, so a step's push (at most G) never overwrites a queued photon.
 template <int G>
 __device__ __forceinline__ uint32_t ring(uint32_t i)
 {
@@ -190,10 +220,17 @@ __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool 
                                            const float4 *rC, Lds<CH> &L, int lane, Acc &c)
 {
     __syncthreads();
-    const uint32_t n = (qlen >= (uint32_t)G) ? (uint32_t)G : (flush ? qlen : 0u);
+    const uint32_t cap = (qlen < (uint32_t)(DRAIN * G)) ? qlen : (uint32_t)(DRAIN * G);
+    const uint32_t n = flush ? cap : (cap & ~(uint32_t)(G - 1));
     const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
-    if (k < n)
-        accumulate<NRM, VCM, CH>(L.queue[QCAP * base + ring<G>(head + k)], K, cos_min, rA, rB, rC, L, lane, c);
+    Cand P[DRAIN];
+#pragma unroll
+    for (int i = 0; i < DRAIN; ++i)
+        if (k + (uint32_t)(i * G) < n)
+            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k + (uint32_t)(i * G))], rA, rB, rC);
+#pragma unroll
+    for (int i = 0; i < DRAIN; ++i)
+        if (k + (uint32_t)(i * G) < n) accumulate<NRM, VCM, CH>(P[i], K, cos_min, L, lane, c);
     qlen -= n;
     head = ring<G>(head + n);
 }
@@ -263,16 +300,18 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const int nyr = c1[1] - c0[1] + 1, nzr = c1[2] - c0[2] + 1;
     const int nrows = any ? nyr * nzr : 0;
     const uint32_t dimx = (uint32_t)hdr->dims[0], dimy = (uint32_t)hdr->dims[1];
+    const float mg = fmaf(r, 1e-4f, hdr->margin_abs);
     const int nbatch = wave_max_i((nrows + G - 1) / G);
 
     for (int b = 0; b < nbatch; ++b) {
         const int row = b * G + j;
         uint32_t st = 0, len = 0;
-        if (row < nrows) {
+        int x0 = 0, x1 = 0;
+        if (row < nrows && row_span(hdr, K.p, r, mg, c0[1] + row % nyr, c0[2] + row / nyr, c0[0], c1[0], x0, x1)) {
             const uint32_t cy = (uint32_t)(c0[1] + row % nyr), cz = (uint32_t)(c0[2] + row / nyr);
             const uint32_t cell = (cz * dimy + cy) * dimx;
-            const uint32_t s0 = cstart[cell + (uint32_t)c0[0]];
-            len = cstart[cell + (uint32_t)c1[0] + 1u] - s0;
+            const uint32_t s0 = cstart[cell + (uint32_t)x0];
+            len = cstart[cell + (uint32_t)x1 + 1u] - s0;
             st = s0 + D.pay_off;
         }
         const uint32_t inc = group_incl_scan<G>(len, j);
@@ -320,7 +359,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                 const uint32_t before = (uint32_t)__popcll(m & below);
                 if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
-                if (__ballot(qlen >= (uint32_t)((QCAP - 1) * G)) != 0ull)
+                if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
                     drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
             }
         }
@@ -329,18 +368,12 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
     __syncthreads();
 
-    // Combine the G lane partials in lane order: lane j of the kernel combines groups j, j + G, ...
-    // from LDS; every lane folds the flux pairs of the kernel's lanes from registers.
-    float fR = 0.0f, xR = 0.0f, fG = 0.0f, xG = 0.0f, fB = 0.0f, xB = 0.0f;
-    for (int l = 0; l < G; ++l) {
-        const int src = base + l;
-        acc2(fR, xR, __shfl(c.fR, src, WAVE));
-        xR += __shfl(c.cR, src, WAVE);
-        acc2(fG, xG, __shfl(c.fG, src, WAVE));
-        xG += __shfl(c.cG, src, WAVE);
-        acc2(fB, xB, __shfl(c.fB, src, WAVE));
-        xB += __shfl(c.cB, src, WAVE);
-    }
+    // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
+    // lane order; the flux pairs are folded across the kernel's lanes by a butterfly.
+    float fR = c.fR, xR = c.cR, fG = c.fG, xG = c.cG, fB = c.fB, xB = c.cB;
+    group_sum_pair<G>(fR, xR);
+    group_sum_pair<G>(fG, xG);
+    group_sum_pair<G>(fB, xB);
     constexpr int COLS = NG * CH;                 // column = channel * NG + group
     constexpr int CPL = (COLS + G - 1) / G;
     float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
@@ -542,10 +575,14 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
     uint32_t cost = 0;
     if (in && stencil(l.hdr, p, l.r[q], c0, c1)) {
         const uint32_t dimx = (uint32_t)l.hdr->dims[0], dimy = (uint32_t)l.hdr->dims[1];
+        const float rq = l.r[q];
+        const float mg = fmaf(rq, 1e-4f, l.hdr->margin_abs);
         for (int cz = c0[2]; cz <= c1[2]; ++cz)
             for (int cy = c0[1]; cy <= c1[1]; ++cy) {
+                int x0, x1;
+                if (!row_span(l.hdr, p, rq, mg, cy, cz, c0[0], c1[0], x0, x1)) continue;
                 const uint32_t cell = ((uint32_t)cz * dimy + (uint32_t)cy) * dimx;
-                cost += l.cstart[cell + (uint32_t)c1[0] + 1u] - l.cstart[cell + (uint32_t)c0[0]];
+                cost += l.cstart[cell + (uint32_t)x1 + 1u] - l.cstart[cell + (uint32_t)x0];
             }
     }
     const uint32_t h = cost > l.heavy_cost ? 1u : 0u;

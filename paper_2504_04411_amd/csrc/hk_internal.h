@@ -302,6 +302,33 @@ __device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], 
     return any;
 }
 
+// Cells [x0, x1] of the stencil row (cy, cz) that can hold a light vertex within r of p, a subrange of
+// the stencil's [c0x, c1x]: every point of the row's y and z slabs lies at least dy and dz from p,
+// so such a vertex has |x - p_x| < sqrt(r^2 - dy^2 - dz^2). The slab distances are reduced by the
+// rounding margin mg and the half-width grown by it, so no vertex within r is ever left out; the
+// rows keep their order, so the in-disk photons reach the sums in the same order as with the full
+// stencil. False when no vertex of the row can lie within r.
+__device__ __forceinline__ bool row_span(const SetHeader *hdr, const float p[3], float r, float mg, int cy, int cz,
+                                         int c0x, int c1x, int &x0, int &x1)
+{
+    float h2 = r * r;
+    const int c[3] = {0, cy, cz};
+#pragma unroll
+    for (int a = 1; a < 3; ++a) {
+        const float w = 1.0f / hdr->cell_inv[a];
+        const float lo = fmaf((float)c[a], w, hdr->dom_lo[a]);
+        const float d = fmaxf(fmaxf(lo - p[a], p[a] - (lo + w)) - mg, 0.0f);
+        h2 = fmaf(-d, d, h2);
+    }
+    if (!(h2 >= 0.0f)) return false;
+    const float h = sqrtf(h2) + mg;
+    const float f0 = floorf((p[0] - h - hdr->dom_lo[0]) * hdr->cell_inv[0]);
+    const float f1 = floorf((p[0] + h - hdr->dom_lo[0]) * hdr->cell_inv[0]);
+    x0 = (int)fminf(fmaxf(f0, (float)c0x), (float)c1x);
+    x1 = (int)fminf(fmaxf(f1, (float)c0x), (float)c1x);
+    return f1 >= (float)c0x && f0 <= (float)c1x;
+}
+
 // Radius histogram bin: floor(-4 log2(r / r1)) clamped to the table.
 __device__ __forceinline__ int radius_bin(float r, float r1)
 {
