@@ -37,10 +37,10 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 
 
-def profiled_traffic(kname):
+def profiled_traffic(kname, tuning):
     """HBM bytes per launch of the gather kernel from the committed rocprofv3 summary, or None when
     the kernel sources changed since the counters were taken (their hash is recorded there) or the
-    summary is of another instance of the kernel."""
+    summary is of another instance of the kernel or another tuning."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "gather_update_box.md")
@@ -53,7 +53,10 @@ def profiled_traffic(kname):
     h = hashlib.sha256()
     for f in ["hk_gather.hip", "hk_internal.h", "hk_kernels.h", "hk_fquant.h"]:
         h.update(open(os.path.join(ROOT, "paper_2504_04411_amd", "csrc", f), "rb").read())
-    if h.hexdigest()[:16] != rec["source_sha256_16"] or rec.get("instance", kname) != kname:
+    if h.hexdigest()[:16] != rec["source_sha256_16"] or rec.get("instance") != kname:
+        return None
+    want = [round(float(tuning[k]), 4) for k in ("cell_scale", "heavy_cost", "lanes_light", "lanes_heavy")]
+    if [round(float(x), 4) for x in rec.get("tuning", [])] != want:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -259,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--tuning", default=None, metavar="CELL,HEAVY,LANES_LIGHT,LANES_HEAVY",
+                    help="fixed tuning instead of the autotuner (profiling runs pin the autotuned setting)")
     ap.add_argument("--tune-at", type=int, default=16,
                     help="untimed iterations before the autotuner samples the state")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-set (config 2) measurement")
@@ -294,12 +299,16 @@ def main():
     est.set_kernels(0, w.kernels.pos, w.kernels.nrm)
     # untimed warm-up; the autotuner samples the state after `tune_at` iterations (radii well below
     # r1, as in most of the timed run), then the timed run restarts from a fresh state
-    n_pre = W if args.no_autotune else max(W, args.tune_at)
+    fixed = args.tuning is not None
+    n_pre = W if (args.no_autotune or fixed) else max(W, args.tune_at)
     for i in range(n_pre):
         est.iterate([0], [dev[i % len(dev)]])
     torch.cuda.synchronize()
+    if fixed:
+        cs, hc, ll, lh = args.tuning.split(",")
+        est.set_tuning(float(cs), int(hc), int(ll), int(lh))
     tuning = est.tuning()
-    if not args.no_autotune:
+    if not (args.no_autotune or fixed):
         # settings timed on scratch copies of the warmed-up state with the next batch
         tuning = est.autotune([0], [dev[n_pre % len(dev)]])
         print(f"# autotuned: {tuning}", file=sys.stderr, flush=True)
@@ -329,9 +338,9 @@ def main():
     launch_ms = prof["gather_ms"] / max(prof["launches"], 1)
     ops = OPS_PER_QUERY * H * K + OPS_PER_PAIR * stats["pairs"]
     achieved = ops / gather_s / 1e12
-    kname = f"gather_update_kernel<true,false,{tuning['lanes_light']},{tuning['lanes_heavy']}>"
+    kname = f"gather_update_kernel<true,false,1,{tuning['lanes_light']},{tuning['lanes_heavy']}>"
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": profiled_traffic(kname),
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": profiled_traffic(kname, tuning),
             "kernel": kname, "avg_launch_ms": round(launch_ms, 4),
             "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
     out = {
@@ -346,7 +355,7 @@ def main():
         "phase_ms_total": {"plan_and_grid": round(prof["grid_ms"], 3), "fcrit_wait": round(prof["fcrit_wait_ms"], 3),
                            "work_list": round(prof["list_ms"], 3), "gather_test_update": round(prof["gather_ms"], 3),
                            "tally": round(prof["tally_ms"], 3)},
-        "tuning": dict(tuning, autotuned=not args.no_autotune),
+        "tuning": dict(tuning, autotuned=not (args.no_autotune or fixed)),
         "pairs_per_query": round(stats["pairs"] / (H * K), 2),
         "candidates_per_pair": round(stats["candidates"] / max(stats["pairs"], 1), 3),
         "final_radius": {"mean": float(radii.mean()), "min": float(radii.min()),
