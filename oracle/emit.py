@@ -28,6 +28,9 @@ the discriminant D = B B - Q is positive and t_s = -B - sqrt(D) lies in (0, t). 
 at L_a + t d_a clamped to [0, 1], with the hit axis set to exactly 1 (d_a > 0) or 0; its normal is
 -1 (d_a > 0) or +1 on the hit axis and 0 elsewhere, and it carries the scene's power in R, G and B.
 A sub-path without a vertex leaves NaN positions, zero normal and zero flux in its slot.
+
+For vertex merging with the vertex-connection half (the next-event connection to the point light),
+a kept vertex also carries dVCM = (4 pi t^2) / |d_a| in float32, computed as (F(4 pi) (t t)) / |d_a|.
 """
 from __future__ import annotations
 
@@ -122,9 +125,12 @@ def directions(J: int, it: int, set_id: int, seed: int):
     return d, done
 
 
-def emit(box: Box, J: int, it: int, set_id: int = 0, seed: int = 1):
+def emit(box: Box, J: int, it: int, set_id: int = 0, seed: int = 1, with_mis: bool = False):
     """The J slots of iteration `it`: pos (3, J), nrm (3, J), flux (3, J) float32 (see the module
-    docstring for the definition)."""
+    docstring for the definition); with `with_mis` also the vertex-merging partials (3, J): dVCM =
+    (4 pi t^2) / |d_a| on the hit axis a, the reciprocal of the area density with which the light
+    pass reaches the vertex (isotropic emission 1 / (4 pi), times cos / t^2 with t the distance and
+    d a unit direction), and dVC = dVM = 0 (nothing precedes a vertex reached from a point light)."""
     d, drawn = directions(J, it, set_id, seed)
     L = np.asarray(box.light, dtype=F32)
     Cs = np.asarray(box.sphere_c, dtype=F32)
@@ -157,4 +163,11 @@ def emit(box: Box, J: int, it: int, set_id: int = 0, seed: int = 1):
         pos[ax] = np.where(keep, p, F32(np.nan))
         nrm[ax] = np.where(keep & on, np.where(d[ax] > 0, F32(-1.0), F32(1.0)), F32(0.0))
         flux[ax] = np.where(keep, F32(box.power), F32(0.0))
-    return pos, nrm, flux
+    if not with_mis:
+        return pos, nrm, flux
+    dh = np.abs(np.choose(np.where(keep, hit_ax, 0), d)).astype(F32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dvcm = (F32(4.0 * np.pi) * (t * t)) / dh
+    mis = np.zeros((3, J), dtype=F32)
+    mis[0] = np.where(keep, dvcm, F32(0.0))
+    return pos, nrm, flux, mis

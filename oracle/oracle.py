@@ -268,10 +268,13 @@ def init_state(H: int, r1: float, r_init: Optional[np.ndarray] = None, rgb: bool
 
 
 def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nthreads: int = 0,
-            fcrit_override=None, gathered: Optional[GatherResult] = None) -> OracleState:
+            fcrit_override=None, gathered: Optional[GatherResult] = None,
+            connect: Optional[np.ndarray] = None) -> OracleState:
     """One iteration for every kernel (Sec. 5.1 steps 1-4, Eq. radiusupdate, Eq. progressive-VCM-estimator).
 
     ``fcrit_override`` (callable m -> F_c) replaces the quantile, for forced-decision tests.
+    ``connect`` ((H, 3), the vertex-connection term of Eq. VCM-estimator for this iteration, computed
+    with the radius this iteration merges with) is added to the iteration's estimate.
     """
     vcm = params.mode == "vcm"
     rgb = getattr(params, "stats", "luma") == "rgb"
@@ -315,6 +318,8 @@ def iterate(params, kernels, st: OracleState, photons, use_grid: bool = True, nt
         st.tau += kernels.cam_beta.T.astype(np.float64) * g.flux * norm[:, None]
     else:
         st.tau += g.flux * norm[:, None]
+    if connect is not None:
+        st.tau += connect
     # radius update (Eq. radiusupdate); float32 as the radius is a float32 quantity on both sides
     lb = lower_bound(params.rmin, params.alpha, i + 1)
     r_new = np.maximum(F32(params.k) * st.r, lb).astype(F32)

@@ -177,3 +177,23 @@ def test_hits_are_on_the_rays():
     with np.errstate(divide="ignore"):
         t = np.min(np.where(dd > 0, (1 - L) / dd, np.where(dd < 0, -L / dd, np.inf)), axis=0)
     assert np.max(np.abs(np.linalg.norm(v, axis=0) - t)) < 5e-6
+
+
+def test_merging_partial_is_the_reciprocal_area_density():
+    """dVCM of a kept vertex is 1 / p_L with p_L = cos(theta) / (4 pi |y - L|^2), the area density of
+    the light pass at the vertex; here recomputed in float64 from the vertex position and normal."""
+    box = E.Box()
+    J = 100_000
+    pos, nrm, flux, mis = E.emit(box, J, it=1, set_id=0, seed=4, with_mis=True)
+    kept = np.isfinite(pos[0])
+    L = np.array(box.light)[:, None]
+    v = pos[:, kept].astype(float) - L
+    d2 = (v * v).sum(0)
+    cos = np.abs((v * nrm[:, kept]).sum(0)) / np.sqrt(d2)
+    pl = cos / (4 * math.pi * d2)
+    ok = cos > 1e-3
+    assert np.max(np.abs(mis[0, kept][ok] * pl[ok] - 1.0)) < 2e-5
+    assert np.all(mis[1:] == 0.0) and np.all(mis[0, ~kept] == 0.0)
+    # the same slots as without the partials
+    p2, n2, f2 = E.emit(box, J, it=1, set_id=0, seed=4)
+    assert np.array_equal(p2, pos, equal_nan=True) and np.array_equal(n2, nrm) and np.array_equal(f2, flux)
