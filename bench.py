@@ -216,11 +216,35 @@ def generated_end_to_end(args, w, tuning):
     g.close()
     est.close()
     gbps = 36.0 * J / (emit_ms * 1e-3) / 1e9
+    # vertex merging with the emission's partials, without and with the vertex connection to the
+    # light (Eq. VCM-estimator), each one graph replay per iteration
+    vcm = {}
+    Hn = w.kernels.n
+    ones = np.ones((3, Hn), np.float32)
+    zeros = np.zeros((3, Hn), np.float32)
+    for connect in (False, True):
+        ev = Estimator(p.r1, mode="vcm", k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+        ev.set_tuning(tuning["cell_scale"], tuning["heavy_cost"], tuning["lanes_light"], tuning["lanes_heavy"])
+        ev.set_kernels(0, w.kernels.pos, w.kernels.nrm, cam_beta=ones, cam_mis=zeros)
+        vb = DevicePhotons(J=J, pos=mk(), flux=mk(), nrm=mk(), mis=mk())
+        gv = ev.capture_box([0], [scene], [args.seed], [vb], connect=connect)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            gv.launch()
+        torch.cuda.synchronize()
+        dtv = time.perf_counter() - t0
+        Lv = ev.radiance(0).cpu().numpy()
+        vcm["merging_and_connection" if connect else "merging_only"] = {
+            "queries_per_s": round(H * K / dtv, 1), "final_mse_vs_analytic": float(((Lv - truth[None, :]) ** 2).mean())}
+        gv.close()
+        ev.close()
     return {"workload": f"box scene, {args.res}x{args.res} hit points, {J} light sub-paths generated on the "
                         f"device per iteration (Philox4x32-10, seed {args.seed}), {K} iterations, one graph "
                         f"replay per iteration",
             "queries_per_s": round(H * K / dt, 1), "ms_per_iteration": round(dt / K * 1e3, 4),
             "final_mse_vs_analytic": mse,
+            "vertex_merging": vcm,
             "emit": {"kernel": "emit_box_kernel", "avg_launch_ms": round(emit_ms, 4),
                      "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                   "frac": round(gbps / HBM_PEAK_GBPS, 4),

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define HK_VERSION 120
+#define HK_VERSION 130
 
 /* status codes */
 #define HK_OK 0
@@ -186,19 +186,41 @@ typedef struct hk_box_scene {
  * the set's hk_set_kernels state) into pos, nrm and flux (device, J floats each, structure of arrays).
  * A slot with a vertex holds its position (the hit coordinate exactly 0 or 1), the wall's inward unit
  * normal and `power` in R, G and B; a slot without one holds NaN positions, a zero normal and zero
- * flux, which the estimator never gathers. The batch for hk_iterate is then {J_emitted = J,
- * n_stored = J, pos, nrm, flux}. J in [0, 2^27 - 1]. Asynchronous on `stream`; nothing advances. */
+ * flux, which the estimator never gathers. When mis is non-NULL (all three device arrays, or NULL),
+ * it receives the vertex-merging partials of each vertex: dVCM = (4 pi t^2) / |d_a| in float32
+ * (t the distance from the light, d_a the unit direction's component on the hit axis: the reciprocal
+ * of the area density with which the light pass reaches the vertex), dVC = dVM = 0; zero in empty
+ * slots. The batch for hk_iterate is then {J_emitted = J, n_stored = J, pos, nrm, flux[, mis]}.
+ * J in [0, 2^27 - 1]. Asynchronous on `stream`; nothing advances. */
 int hk_emit_box(hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *scene, uint64_t seed,
-                int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3], hipStream_t stream);
+                int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3], float *const mis[3],
+                hipStream_t stream);
+
+/* Vertex connection for the box scene (the VC sum of Eq. VCM-estimator, here the connection of each
+ * camera vertex x to the point light): adds w_VC beta_C I cos(theta_x) V(x) / d^2 per channel to the
+ * set's running estimate for the iteration about to run, with the balance-heuristic weight of Eq.
+ * mis-weight against merging, w_VC = 1 / (1 + J pi r^2 cos(theta_x) / (4 pi d^2)), r the camera
+ * vertex's current radius (the one the next hk_iterate merges with), J = J_emitted of that
+ * iteration, I = power / (4 pi), V the float32 shadow test of the segment x -> light against the
+ * sphere (with w = light - x, dist = sqrt((w_x w_x + w_y w_y) + w_z w_z), u = w / dist, o = x - C,
+ * B = (u_x o_x + u_y o_y) + u_z o_z, Q = ((o_x o_x + o_y o_y) + o_z o_z) - R R: blocked when
+ * B B - Q > 0 and -B - sqrt(B B - Q) lies in (0, dist)). Merging then carries the complementary
+ * weight when the light vertices carry hk_emit_box's partials and the camera partials are zero.
+ * Needs vertex-merging mode and camera vertices with normals (HK_E_BAD_STATE otherwise). Call it on
+ * the same stream before the hk_iterate of the iteration. */
+int hk_connect_box(hk_ctx *ctx, int set_id, void *state, const hk_box_scene *scene, uint64_t J_emitted,
+                   hipStream_t stream);
 
 /* hk_graph_create with the generation of every set's batch in front: each launch of the graph
- * writes the batches ph[s] (device arrays; they must be writable, with n_stored == J_emitted and
- * the normal arrays given) with hk_emit_box's definition for scenes[s] and seeds[s] and the set's
- * current iteration, then runs the iteration on them. One replay is one complete iteration with no
+ * writes the batches ph[s] (device arrays; they must be writable, with n_stored == J_emitted, the
+ * normal arrays given, and in vertex-merging mode the mis arrays) with hk_emit_box's definition for
+ * scenes[s] and seeds[s] and the set's current iteration, then (flags & HK_BOX_CONNECT) runs
+ * hk_connect_box for every set, then the iteration. One replay is one complete iteration with no
  * host work beyond the launch. */
+#define HK_BOX_CONNECT 1
 int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_box_scene *scenes,
                         const uint64_t *seeds, const hk_photons *ph, void *const *state, void *workspace,
-                        size_t workspace_bytes, hk_graph **out);
+                        size_t workspace_bytes, int flags, hk_graph **out);
 
 /* Times one iteration of the given sets for each of 36 settings (cell_scale 0.7 / 1 / 1.4 x
  * lanes_light 4 / 8 / 16 x heavy_cost 1024 / 2048 / 4096 / 16384) and keeps the fastest in the context

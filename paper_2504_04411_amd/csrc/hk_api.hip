@@ -569,7 +569,8 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
 
 // Captures [light-vertex generation of every set, when `emit` is given] + one iteration.
 static int graph_capture(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
-                         void *workspace, size_t workspace_bytes, const EmitLaunch *emit, hk_graph **out)
+                         void *workspace, size_t workspace_bytes, const EmitLaunch *emit,
+                         const ConnectLaunch *conn, hk_graph **out)
 {
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
@@ -581,6 +582,8 @@ static int graph_capture(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_p
     HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
     if (emit)
         for (int s = 0; s < n_sets; ++s) launch_emit_box(emit[s], ctx->cap);
+    if (conn)
+        for (int s = 0; s < n_sets; ++s) launch_connect_box(conn[s], ctx->cap);
     rc = enqueue(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, ctx->cap, false, nullptr, &g->all);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
@@ -612,7 +615,7 @@ extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, cons
     *out = nullptr;
     const int rc = validate(ctx, n_sets, set_ids, ph, state, workspace);
     if (rc) return rc;
-    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, nullptr, out);
+    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, nullptr, nullptr, out);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -620,7 +623,8 @@ extern "C" int hk_graph_create(hk_ctx *ctx, int n_sets, const int *set_ids, cons
 // ------------------------------------------------------------------------------------------------
 
 static int emit_args(const hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *sc, uint64_t seed,
-                     int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3], EmitLaunch *e)
+                     int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3],
+                     float *const mis[3], EmitLaunch *e)
 {
     if (set_id < 0 || set_id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", set_id);
     const SetInfo &S = ctx->sets[set_id];
@@ -639,6 +643,8 @@ static int emit_args(const hk_ctx *ctx, int set_id, const void *state, const hk_
         if (!pos || !nrm || !flux) return fail(HK_E_INVALID_ARG, "output arrays are NULL");
         for (int a = 0; a < 3; ++a)
             if (!pos[a] || !nrm[a] || !flux[a]) return fail(HK_E_INVALID_ARG, "output arrays are NULL");
+        if (mis && (mis[0] || mis[1] || mis[2]) && !(mis[0] && mis[1] && mis[2]))
+            return fail(HK_E_INVALID_ARG, "mis must be all NULL or all set");
     }
     const Layout L = layout_of(ctx, S.H);
     *e = EmitLaunch{};
@@ -650,6 +656,7 @@ static int emit_args(const hk_ctx *ctx, int set_id, const void *state, const hk_
             e->pos[a] = pos[a];
             e->nrm[a] = nrm[a];
             e->flux[a] = flux[a];
+            e->mis[a] = mis ? mis[a] : nullptr;
         }
     }
     e->R = sc->sphere_r;
@@ -663,11 +670,11 @@ static int emit_args(const hk_ctx *ctx, int set_id, const void *state, const hk_
 
 extern "C" int hk_emit_box(hk_ctx *ctx, int set_id, const void *state, const hk_box_scene *scene, uint64_t seed,
                            int64_t J, float *const pos[3], float *const nrm[3], float *const flux[3],
-                           hipStream_t stream)
+                           float *const mis[3], hipStream_t stream)
 {
     if (!ctx) return fail(HK_E_INVALID_ARG, "hk_emit_box: NULL context");
     EmitLaunch e;
-    const int rc = emit_args(ctx, set_id, state, scene, seed, J, pos, nrm, flux, &e);
+    const int rc = emit_args(ctx, set_id, state, scene, seed, J, pos, nrm, flux, mis, &e);
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     launch_emit_box(e, stream);
@@ -675,9 +682,51 @@ extern "C" int hk_emit_box(hk_ctx *ctx, int set_id, const void *state, const hk_
     return HK_OK;
 }
 
+static int connect_args(const hk_ctx *ctx, int set_id, void *state, const hk_box_scene *sc, uint64_t J,
+                        ConnectLaunch *c)
+{
+    if (set_id < 0 || set_id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", set_id);
+    const SetInfo &S = ctx->sets[set_id];
+    if (!S.init) return fail(HK_E_BAD_STATE, "set %d has no kernels (call hk_set_kernels)", set_id);
+    if (ctx->p.mode != HK_MODE_VCM) return fail(HK_E_BAD_STATE, "the connection needs vertex-merging mode");
+    if (!S.has_nrm) return fail(HK_E_BAD_STATE, "the connection needs the camera vertices' normals");
+    if (!state || !aligned(state)) return fail(HK_E_INVALID_ARG, "state must be non-NULL and 256-byte aligned");
+    if (!sc) return fail(HK_E_INVALID_ARG, "scene is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(sc->light[a]) || !isfinite(sc->sphere_c[a]))
+            return fail(HK_E_INVALID_ARG, "light and sphere centre must be finite");
+    if (!(sc->sphere_r >= 0.0f && isfinite(sc->sphere_r))) return fail(HK_E_INVALID_ARG, "sphere radius must be >= 0");
+    if (!isfinite(sc->power)) return fail(HK_E_INVALID_ARG, "power must be finite");
+    if (J < 1 || J > (uint64_t)1 << 52) return fail(HK_E_INVALID_ARG, "J must be in [1, 2^52]");
+    *c = ConnectLaunch{};
+    c->st = make_view(state, layout_of(ctx, S.H));
+    c->H = S.H;
+    for (int a = 0; a < 3; ++a) {
+        c->L[a] = sc->light[a];
+        c->C[a] = sc->sphere_c[a];
+    }
+    c->R = sc->sphere_r;
+    c->intensity = (float)((double)sc->power / (4.0 * M_PI));
+    c->Jf = (float)J;
+    return HK_OK;
+}
+
+extern "C" int hk_connect_box(hk_ctx *ctx, int set_id, void *state, const hk_box_scene *scene, uint64_t J_emitted,
+                              hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_connect_box: NULL context");
+    ConnectLaunch c;
+    const int rc = connect_args(ctx, set_id, state, scene, J_emitted, &c);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_connect_box(c, stream);
+    HIP_TRY(hipGetLastError());
+    return HK_OK;
+}
+
 extern "C" int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_box_scene *scenes,
                                    const uint64_t *seeds, const hk_photons *ph, void *const *state, void *workspace,
-                                   size_t workspace_bytes, hk_graph **out)
+                                   size_t workspace_bytes, int flags, hk_graph **out)
 {
     if (!ctx || !out) return fail(HK_E_INVALID_ARG, "hk_graph_create_box: NULL argument");
     *out = nullptr;
@@ -691,16 +740,29 @@ extern "C" int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, 
             return fail(HK_E_INVALID_ARG, "set %d: generated batches store every slot (n_stored == J_emitted)", set_ids[s]);
         if (!P.nrm[0] || !P.nrm[1] || !P.nrm[2])
             return fail(HK_E_INVALID_ARG, "set %d: generated batches need the normal arrays", set_ids[s]);
-        float *pos[3], *nrm[3], *flux[3];
+        float *pos[3], *nrm[3], *flux[3], *mis[3];
         for (int a = 0; a < 3; ++a) {
             pos[a] = const_cast<float *>(P.pos[a]);
             nrm[a] = const_cast<float *>(P.nrm[a]);
             flux[a] = const_cast<float *>(P.flux[a]);
+            mis[a] = const_cast<float *>(P.mis[a]);
         }
-        rc = emit_args(ctx, set_ids[s], state[s], &scenes[s], seeds[s], P.n_stored, pos, nrm, flux, &em[s]);
+        rc = emit_args(ctx, set_ids[s], state[s], &scenes[s], seeds[s], P.n_stored, pos, nrm, flux, mis, &em[s]);
         if (rc) return rc;
+        if (ctx->p.mode == HK_MODE_VCM && !(mis[0] && mis[1] && mis[2]))
+            return fail(HK_E_INVALID_ARG, "set %d: vertex merging needs the mis arrays", set_ids[s]);
     }
-    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, em.data(), out);
+    if (flags & ~HK_BOX_CONNECT) return fail(HK_E_INVALID_ARG, "unknown flags");
+    std::vector<ConnectLaunch> cn;
+    if (flags & HK_BOX_CONNECT) {
+        cn.resize(n_sets);
+        for (int s = 0; s < n_sets; ++s) {
+            rc = connect_args(ctx, set_ids[s], state[s], &scenes[s], ph[s].J_emitted, &cn[s]);
+            if (rc) return rc;
+        }
+    }
+    return graph_capture(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, em.data(),
+                         cn.empty() ? nullptr : cn.data(), out);
 }
 
 extern "C" int hk_graph_launch(hk_graph *g, hipStream_t stream)

@@ -29,6 +29,7 @@
 namespace hk {
 
 constexpr int EMIT_THREADS = 256;
+constexpr float FOUR_PI_F = 12.566370614359172f;
 constexpr int EMIT_BLOCKS = 8;      // Philox blocks per slot: 16 direction attempts
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
@@ -108,6 +109,62 @@ __global__ __launch_bounds__(EMIT_THREADS) void emit_box_kernel(EmitLaunch e)
         e.nrm[ax][j] = keep ? n : 0.0f;
         e.flux[ax][j] = keep ? e.power : 0.0f;
     }
+    if (e.mis[0]) {
+        // reciprocal of the area density of the vertex: isotropic emission 1 / (4 pi) times
+        // cos / t^2, the cosine being the direction's component on the hit axis
+        const float dh = fabsf(hit == 0 ? d[0] : hit == 1 ? d[1] : d[2]);
+        const float dvcm = (FOUR_PI_F * (t * t)) / dh;
+        e.mis[0][j] = keep ? dvcm : 0.0f;
+        e.mis[1][j] = 0.0f;
+        e.mis[2][j] = 0.0f;
+    }
+}
+
+// Next-event connection of camera vertex q to the point light (the VC technique of the VCM
+// estimator for the box scene) with the balance-heuristic weight against merging:
+//   w_VC = 1 / (1 + eta p_L(x)),  eta = J pi r^2,  p_L(x) = cos / (4 pi d^2),
+// adding w_VC beta_C I cos V / d^2 to the iteration's flux-density estimate (compensated pairs).
+// The shadow test is float32 in the stated operation order; the radius is the one this iteration
+// merges with (the kernel runs before the gather of the iteration).
+__global__ __launch_bounds__(256) void connect_box_kernel(ConnectLaunch c)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= c.H) return;
+    const StateView &st = c.st;
+    const float px = st.pos[0][q], py = st.pos[1][q], pz = st.pos[2][q];
+    const float nx = st.nrm[0][q], ny = st.nrm[1][q], nz = st.nrm[2][q];
+    const float r = st.r[q];
+    // shadow test of the segment x -> light
+    const float wx = c.L[0] - px, wy = c.L[1] - py, wz = c.L[2] - pz;
+    const float d2 = (wx * wx + wy * wy) + wz * wz;
+    const float dist = __builtin_sqrtf(d2);
+    const float ux = wx / dist, uy = wy / dist, uz = wz / dist;
+    const float ox = px - c.C[0], oy = py - c.C[1], oz = pz - c.C[2];
+    const float B = (ux * ox + uy * oy) + uz * oz;
+    const float Q = ((ox * ox + oy * oy) + oz * oz) - c.R * c.R;
+    const float D = B * B - Q;
+    const float t0 = -B - __builtin_sqrtf(fmaxf(D, 0.0f));
+    const bool blocked = D > 0.0f && t0 > 0.0f && t0 < dist;
+    const float cs = fmaxf(0.0f, (ux * nx + uy * ny) + uz * nz);
+    const float eta = c.Jf * (PI_F * (r * r));
+    const float pl = cs / (FOUR_PI_F * d2);
+    const float w = 1.0f / (1.0f + eta * pl);
+    const float e = blocked ? 0.0f : ((w * c.intensity) * cs) / d2;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float *ts = st.tau0 + (size_t)(2 * ch) * st.astride;
+        float *tc = st.tau0 + (size_t)(2 * ch + 1) * st.astride;
+        float sv = ts[q], cv = tc[q];
+        acc2(sv, cv, st.cb[ch][q] * e);
+        ts[q] = sv;
+        tc[q] = cv;
+    }
+}
+
+void launch_connect_box(const ConnectLaunch &c, hipStream_t s)
+{
+    if (c.H <= 0) return;
+    connect_box_kernel<<<(int)cdiv(c.H, 256), 256, 0, s>>>(c);
 }
 
 void launch_emit_box(const EmitLaunch &e, hipStream_t s)

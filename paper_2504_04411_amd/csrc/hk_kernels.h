@@ -152,7 +152,17 @@ struct EmitLaunch {
     uint32_t key0, key1, set_id;
     int64_t J;
     float *pos[3], *nrm[3], *flux[3];
+    float *mis[3];           // vertex-merging partials (dVCM, dVC, dVM), or all NULL
 };
 void launch_emit_box(const EmitLaunch &e, hipStream_t s);
+
+// vertex connection of every camera vertex to the box scene's point light (next-event estimation),
+// weighted against merging and added to the set's running estimate
+struct ConnectLaunch {
+    StateView st;
+    int64_t H;
+    float L[3], C[3], R, intensity, Jf;
+};
+void launch_connect_box(const ConnectLaunch &c, hipStream_t s);
 
 }  // namespace hk

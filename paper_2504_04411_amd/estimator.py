@@ -133,22 +133,29 @@ class Estimator:
                  out: Optional[DevicePhotons] = None) -> DevicePhotons:
         """Generates the set's next batch of J light-vertex slots on the device (hk_emit_box); empty
         slots hold NaN positions. Writes into `out` when given (same J), else into new tensors."""
+        vcm = self.params.mode == hk.HK_MODE_VCM
         if out is None:
             mk = lambda: torch.empty((3, J), dtype=torch.float32, device=self.device)  # noqa: E731
-            out = DevicePhotons(J=J, pos=mk(), flux=mk(), nrm=mk())
-        if out.J != J or out.n != J or out.nrm is None:
-            raise ValueError("out must hold J slots with normals")
+            out = DevicePhotons(J=J, pos=mk(), flux=mk(), nrm=mk(), mis=mk() if vcm else None)
+        if out.J != J or out.n != J or out.nrm is None or (vcm and out.mis is None):
+            raise ValueError("out must hold J slots with normals (and partials for vertex merging)")
         hk.hk_emit_box(self.ctx, set_id, self.states[set_id].data_ptr(), scene, seed, J, _rows(out.pos),
-                       _rows(out.nrm), _rows(out.flux), self.stream)
+                       _rows(out.nrm), _rows(out.flux), self.stream, mis=_rows(out.mis))
         return out
 
-    def capture_box(self, set_ids: Sequence[int], scenes, seeds, photons: Sequence[DevicePhotons]) -> "Graph":
-        """Captures generation of every set's batch into `photons` plus one iteration on them: each
-        launch of the graph is one complete iteration."""
+    def connect_box(self, set_id: int, scene: hk.hk_box_scene, J: int):
+        """Adds the vertex-connection term (hk_connect_box) for the iteration about to run."""
+        hk.hk_connect_box(self.ctx, set_id, self.states[set_id].data_ptr(), scene, J, self.stream)
+
+    def capture_box(self, set_ids: Sequence[int], scenes, seeds, photons: Sequence[DevicePhotons],
+                    connect: bool = False) -> "Graph":
+        """Captures generation of every set's batch into `photons` (and, with `connect`, the vertex
+        connection) plus one iteration on them: each launch of the graph is one complete iteration."""
         wsb = self.workspace_for(photons, set_ids)
         ws = self._workspace(wsb)
         g = hk.hk_graph_create_box(self.ctx, list(set_ids), list(scenes), list(seeds), [p.struct() for p in photons],
-                                   [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel())
+                                   [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel(),
+                                   hk.HK_BOX_CONNECT if connect else 0)
         return Graph(self, g, ws, list(photons))
 
     def autotune(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]) -> dict:

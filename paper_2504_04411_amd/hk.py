@@ -81,9 +81,10 @@ def lib():
                                  c.c_size_t, c.POINTER(_vp)], c.c_int),
             "hk_graph_create_box": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_box_scene),
                                      c.POINTER(c.c_uint64), c.POINTER(hk_photons), c.POINTER(_vp), _vp, c.c_size_t,
-                                     c.POINTER(_vp)], c.c_int),
+                                     c.c_int, c.POINTER(_vp)], c.c_int),
             "hk_emit_box": ([_vp, c.c_int, _vp, c.POINTER(hk_box_scene), c.c_uint64, c.c_int64, _vp * 3, _vp * 3,
-                             _vp * 3, _vp], c.c_int),
+                             _vp * 3, _vp * 3, _vp], c.c_int),
+            "hk_connect_box": ([_vp, c.c_int, _vp, c.POINTER(hk_box_scene), c.c_uint64, _vp], c.c_int),
             "hk_graph_launch": ([_vp, _vp], c.c_int),
             "hk_graph_destroy": ([_vp], c.c_int),
             "hk_autotune": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp),
@@ -257,17 +258,24 @@ def box_scene(light, sphere_c, sphere_r, power) -> hk_box_scene:
     return sc
 
 
-def hk_emit_box(ctx, set_id, state, scene: hk_box_scene, seed, J, pos, nrm, flux, stream):
+HK_BOX_CONNECT = 1
+
+
+def hk_emit_box(ctx, set_id, state, scene: hk_box_scene, seed, J, pos, nrm, flux, stream, mis=None):
     check(lib().hk_emit_box(ctx, int(set_id), state, ctypes.byref(scene), int(seed), int(J), _arr3(pos), _arr3(nrm),
-                            _arr3(flux), stream))
+                            _arr3(flux), _arr3(mis), stream))
 
 
-def hk_graph_create_box(ctx, set_ids, scenes, seeds, photons, states, workspace, workspace_bytes) -> int:
+def hk_connect_box(ctx, set_id, state, scene: hk_box_scene, J_emitted, stream):
+    check(lib().hk_connect_box(ctx, int(set_id), state, ctypes.byref(scene), int(J_emitted), stream))
+
+
+def hk_graph_create_box(ctx, set_ids, scenes, seeds, photons, states, workspace, workspace_bytes, flags=0) -> int:
     n, ids, phs, sts = _set_arrays(set_ids, photons, states)
     scs = (hk_box_scene * n)(*scenes)
     sds = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
     g = _vp()
-    check(lib().hk_graph_create_box(ctx, n, ids, scs, sds, phs, sts, workspace, int(workspace_bytes),
+    check(lib().hk_graph_create_box(ctx, n, ids, scs, sds, phs, sts, workspace, int(workspace_bytes), int(flags),
                                     ctypes.byref(g)))
     return g.value
 

@@ -82,11 +82,14 @@ class Tracker:
         self.name = name or w.name
         self.nseen = np.zeros(self.idx.size, np.int64)     # retained samples before this iteration
 
-    def step(self, est: Estimator, set_id: int, ph):
-        """Advances the oracle by the iteration the GPU just ran with photons ph and compares."""
+    def step(self, est: Estimator, set_id: int, ph, connect_fn=None):
+        """Advances the oracle by the iteration the GPU just ran with photons ph and compares.
+        `connect_fn(kernels, r)` gives the oracle's vertex-connection term for the tracked kernels at
+        the oracle's own radii, when the GPU iteration had one."""
         idx, ost, alive, rep = self.idx, self.ost, self.alive, self.rep
         it = rep.iterations
-        O.iterate(self.p, self.oks, ost, ph)
+        extra = connect_fn(self.oks, ost.r) if connect_fn is not None else None
+        O.iterate(self.p, self.oks, ost, ph, connect=extra)
         d = {k: v.cpu().numpy()[idx] for k, v in est.debug(set_id).items()}
         rg = est.radii(set_id).cpu().numpy()[idx]
         cnt = d["count"].astype(np.uint32)
