@@ -279,6 +279,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         }
         r = fslot(SL_R)[q];
     }
+    const uint32_t t_prev = active ? uslot(SL_T)[q] : 0u;
     K.r2 = active ? r * r : -1.0f;
     K.inv_eta = 0.0f;
     K.wc = 0.0f;
@@ -364,16 +365,9 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             }
         }
     }
-    while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
-    __syncthreads();
-
-    // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
-    // lane order; the flux pairs are folded across the kernel's lanes by a butterfly.
-    float fR = c.fR, xR = c.cR, fG = c.fG, xG = c.cG, fB = c.fB, xB = c.cB;
-    group_sum_pair<G>(fR, xR);
-    group_sum_pair<G>(fG, xG);
-    group_sum_pair<G>(fB, xB);
+    // The epilogue's state reads are issued before the last drains, so their latency overlaps them:
+    // the retained sums of the lane's columns, the kept-iteration count's J sums and critical
+    // value, and (first lane) the photons seen and the running estimate.
     constexpr int COLS = NG * CH;                 // column = channel * NG + group
     constexpr int CPL = (COLS + G - 1) / G;
     float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
@@ -387,6 +381,29 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             Q[k] = fslot(SL_SQ + 4 * col + 2)[q];
             cQ[k] = fslot(SL_SQ + 4 * col + 3)[q];
         }
+    }
+    const uint32_t t_new = t_prev + 1u;
+    const double m = active ? mprefix[iter] - mprefix[iter - (int)t_new] : 2.0;
+    const bool lead = active && j == 0;
+    const double Fc = lead ? fctab[t_new] : 0.0;
+    const uint32_t seen_prev = lead ? uslot(SL_NSEEN)[q] : 0u;
+    float tv[6];
+#pragma unroll
+    for (int cc = 0; cc < 6; ++cc) tv[cc] = lead ? fslot(SL_TAU + cc)[q] : 0.0f;
+
+    while (__ballot(qlen > 0u) != 0ull)
+        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+    __syncthreads();
+
+    // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
+    // lane order; the flux pairs are folded across the kernel's lanes by a butterfly.
+    float fR = c.fR, xR = c.cR, fG = c.fG, xG = c.cG, fB = c.fB, xB = c.cB;
+    group_sum_pair<G>(fR, xR);
+    group_sum_pair<G>(fG, xG);
+    group_sum_pair<G>(fB, xB);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int col = j + k * G;
         if (col < COLS) {
             for (int l = 0; l < G; ++l) {
                 const float4 x = L.slot[col][base + l];
@@ -398,8 +415,6 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         }
     }
     const uint32_t cnt_q = group_sum_u<G>(c.cnt);
-    const uint32_t t_new = active ? uslot(SL_T)[q] + 1u : 1u;
-    const double m = active ? mprefix[iter] - mprefix[iter - (int)t_new] : 2.0;
     // per channel: total, between- and within-group sums of squares (Eq. f-statistic), the lane's
     // columns first, then summed over the kernel's lanes
     double sg[CPL], qg[CPL];
@@ -438,8 +453,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 
     int shrink = 0;
     if (active && j == 0) {
-        const uint32_t seen = uslot(SL_NSEEN)[q] + cnt_q;
-        const double Fc = fctab[t_new];
+        const uint32_t seen = seen_prev + cnt_q;
         // one test per channel: reject when any channel rejects; report the largest F
         double F = (double)NAN;
 #pragma unroll
@@ -456,9 +470,6 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             eG = K.cb[1] * eG;
             eB = K.cb[2] * eB;
         }
-        float tv[6];
-#pragma unroll
-        for (int cc = 0; cc < 6; ++cc) tv[cc] = fslot(SL_TAU + cc)[q];
         acc2(tv[0], tv[1], eR);
         acc2(tv[2], tv[3], eG);
         acc2(tv[4], tv[5], eB);
