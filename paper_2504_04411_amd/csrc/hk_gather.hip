@@ -302,13 +302,15 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const int nrows = any ? nyr * nzr : 0;
     const uint32_t dimx = (uint32_t)hdr->dims[0], dimy = (uint32_t)hdr->dims[1];
     const float mg = fmaf(r, 1e-4f, hdr->margin_abs);
+    const float wy = 1.0f / hdr->cell_inv[1], wz = 1.0f / hdr->cell_inv[2];
     const int nbatch = wave_max_i((nrows + G - 1) / G);
 
     for (int b = 0; b < nbatch; ++b) {
         const int row = b * G + j;
         uint32_t st = 0, len = 0;
         int x0 = 0, x1 = 0;
-        if (row < nrows && row_span(hdr, K.p, r, mg, c0[1] + row % nyr, c0[2] + row / nyr, c0[0], c1[0], x0, x1)) {
+        if (row < nrows &&
+            row_span(hdr, K.p, r, mg, wy, wz, c0[1] + row % nyr, c0[2] + row / nyr, c0[0], c1[0], x0, x1)) {
             const uint32_t cy = (uint32_t)(c0[1] + row % nyr), cz = (uint32_t)(c0[2] + row / nyr);
             const uint32_t cell = (cz * dimy + cy) * dimx;
             const uint32_t s0 = cstart[cell + (uint32_t)x0];
@@ -588,10 +590,11 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
         const uint32_t dimx = (uint32_t)l.hdr->dims[0], dimy = (uint32_t)l.hdr->dims[1];
         const float rq = l.r[q];
         const float mg = fmaf(rq, 1e-4f, l.hdr->margin_abs);
+        const float wy = 1.0f / l.hdr->cell_inv[1], wz = 1.0f / l.hdr->cell_inv[2];
         for (int cz = c0[2]; cz <= c1[2]; ++cz)
             for (int cy = c0[1]; cy <= c1[1]; ++cy) {
                 int x0, x1;
-                if (!row_span(l.hdr, p, rq, mg, cy, cz, c0[0], c1[0], x0, x1)) continue;
+                if (!row_span(l.hdr, p, rq, mg, wy, wz, cy, cz, c0[0], c1[0], x0, x1)) continue;
                 const uint32_t cell = ((uint32_t)cz * dimy + (uint32_t)cy) * dimx;
                 cost += l.cstart[cell + (uint32_t)x1 + 1u] - l.cstart[cell + (uint32_t)x0];
             }
@@ -616,6 +619,9 @@ void launch_cost(const ListLaunch &l, hipStream_t s)
     cost_kernel<<<(int)cdiv(l.H, 256), 256, 0, s>>>(l);
 }
 
+// Stable partition of the batch's work list, heavy kernels first, in kernel order within each list
+// (the Morton order of each set, sets in batch order): the order keeps neighbouring kernels together,
+// which the gather's cache reuse depends on.
 __global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const uint32_t *offs, const uint32_t *ids,
                                                     int64_t n, uint32_t *heavy, uint32_t *light, uint32_t *counts)
 {

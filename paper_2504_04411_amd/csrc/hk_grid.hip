@@ -4,7 +4,7 @@
 //   plan      picks the cell size from the radius distribution of the previous update
 //   keys      cell index of every photon (x fastest), KEY_OUTSIDE outside the grid domain
 //   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
-//             a three-phase exclusive scan and a wave-ballot stable scatter
+//             per-digit prefix over the blocks and digit totals, and a wave-ballot stable scatter
 //   permute   inverse permutation, then a coalesced read / scattered write of the photon payload
 //             into sorted order (three float4 per photon, with the photon's luminance for PPM)
 //   cstart    photons per cell (wave-aggregated atomics on the sorted keys), exclusive scan:
@@ -50,9 +50,24 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
     return off + inc - v;
 }
 
-__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *d, int64_t len, uint32_t *part)
+// Length of a scan whose array is sized for a bound but whose live part is known on the device only
+// (the cell counts of this iteration's plan): min(len, *dlen + extra), or len when dlen is NULL.
+__device__ __forceinline__ int64_t live_len(int64_t len, const uint32_t *dlen, int extra)
 {
+    if (!dlen) return len;
+    const int64_t l = (int64_t)*dlen + extra;
+    return l < len ? l : len;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *d, int64_t len, uint32_t *part,
+                                                          const uint32_t *dlen, int extra)
+{
+    len = live_len(len, dlen, extra);
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    if (base >= len) {
+        if (threadIdx.x == 0) part[blockIdx.x] = 0u;
+        return;
+    }
     uint32_t s = 0;
     for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
         const int64_t k = base + i;
@@ -76,9 +91,12 @@ __global__ __launch_bounds__(256) void scan_parts_kernel(uint32_t *part, int npa
     }
 }
 
-__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len, const uint32_t *part)
+__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len, const uint32_t *part,
+                                                        const uint32_t *dlen, int extra)
 {
     constexpr int PER = SCAN_TILE / 256;
+    len = live_len(len, dlen, extra);
+    if ((int64_t)blockIdx.x * SCAN_TILE >= len) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
     uint32_t v[PER];
     uint32_t s = 0;
@@ -98,12 +116,12 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len
     }
 }
 
-void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s)
+void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const uint32_t *dlen, int extra)
 {
     const int nparts = (int)cdiv(len, SCAN_TILE);
-    scan_reduce_kernel<<<nparts, 256, 0, s>>>(d, len, part);
+    scan_reduce_kernel<<<nparts, 256, 0, s>>>(d, len, part, dlen, extra);
     scan_parts_kernel<<<1, 256, 0, s>>>(part, nparts);
-    scan_down_kernel<<<nparts, 256, 0, s>>>(d, len, part);
+    scan_down_kernel<<<nparts, 256, 0, s>>>(d, len, part, dlen, extra);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -125,17 +143,38 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *key
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter: items are visited in rounds of 256 consecutive keys; inside a round the rank of a
-// key among equal digits is (count in earlier rounds) + (count in lower waves) + (lower lanes of the
-// same wave, from eight ballots).
+// One block per digit d: the blocks' counts of d become their exclusive prefix over the blocks (in
+// place), and the digit's total goes to dtot[d].
+__global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nblk, uint32_t *dtot)
+{
+    uint32_t *h = hist + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblk; base += 256) {
+        const int k = base + threadIdx.x;
+        const uint32_t v = k < nblk ? h[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot);
+        if (k < nblk) h[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
+// Stable scatter: a block's first position for digit d is the exclusive scan of the digit totals at
+// d plus the block's prefix within d. Items are visited in rounds of 256 consecutive keys; inside a
+// round the rank of a key among equal digits is (count in earlier rounds) + (count in lower waves)
+// + (lower lanes of the same wave, from eight ballots).
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                 uint32_t *kout, uint32_t *vout, int64_t n,
-                                                                int shift, const uint32_t *offs, int nblk)
+                                                                int shift, const uint32_t *offs, int nblk,
+                                                                const uint32_t *dtot)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    uint32_t all;
+    const uint32_t dbase = block_excl_scan(dtot[tid], &all);
+    run[tid] = dbase + offs[(int64_t)tid * nblk + blockIdx.x];
     for (int i = 0; i < 4; ++i) wcnt[i][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -178,8 +217,8 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
     uint32_t *vspare = vA;
     for (int shift = 0; shift < bits; shift += 8) {
         rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
-        excl_scan(hist, (int64_t)256 * nblk, part, s);
-        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk);
+        rs_offsets_kernel<<<256, 256, 0, s>>>(hist, nblk, part);
+        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk, part);
         uint32_t *kt = ki;
         ki = ko;
         ko = kt;
@@ -327,10 +366,10 @@ __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, 
     pay[2 * ps + q] = make_float4(R, G, B, dvcm);
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t n)
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t n, const uint32_t *dlen, int extra)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    if (i < live_len(n, dlen, extra)) p[i] = 0u;
 }
 
 // Photons per cell from the sorted keys: the first lane of every run of equal keys inside a
@@ -354,8 +393,10 @@ __global__ __launch_bounds__(256) void cell_count_kernel(const SetHeader *hdr, c
 void build_grid(const GridLaunch &g, hipStream_t s)
 {
     const int64_t n = g.n;
-    const int64_t nc = (int64_t)g.ncells_bound + 1;     // counts of every possible cell, then their scan
-    zero_kernel<<<(int)cdiv(nc, 256), 256, 0, s>>>(g.cstart, nc);
+    // counts of every cell of this iteration's plan, then their scan: the arrays are sized for the
+    // workspace bound, the plan's cell count (on the device) limits the work
+    const int64_t nc = (int64_t)g.ncells_bound + 1;
+    zero_kernel<<<(int)cdiv(nc, 256), 256, 0, s>>>(g.cstart, nc, &g.hdr->ncells, 1);
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
@@ -366,7 +407,7 @@ void build_grid(const GridLaunch &g, hipStream_t s)
         permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pstride);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
-    excl_scan(g.cstart, nc, g.part3, s);
+    excl_scan(g.cstart, nc, g.part3, s, &g.hdr->ncells, 1);
 }
 
 // ------------------------------------------------------------------------------------------------

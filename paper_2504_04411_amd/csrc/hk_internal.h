@@ -207,7 +207,8 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     W.valB = take(4 * (size_t)nmax);
     const int64_t nblk = cdiv(nmax, RS_TILE);
     W.hist = take(4 * (size_t)(256 * nblk));
-    W.part = take(4 * (size_t)(cdiv(256 * nblk, SCAN_TILE) + 1));
+    const int64_t nscan = cdiv(256 * nblk, SCAN_TILE) + 1;
+    W.part = take(4 * (size_t)(nscan > 256 ? nscan : 256));   // scan partials, or the 256 digit totals
     W.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
     W.cstart = take(4 * (size_t)(cells + 1));
     W.pay = take(16 * (size_t)W.n_total * PAY_VEC + 256);     // plane stride: n_total photons
@@ -307,17 +308,17 @@ __device__ __forceinline__ bool stencil(const SetHeader *hdr, const float p[3], 
 // so such a vertex has |x - p_x| < sqrt(r^2 - dy^2 - dz^2). The slab distances are reduced by the
 // rounding margin mg and the half-width grown by it, so no vertex within r is ever left out; the
 // rows keep their order, so the in-disk photons reach the sums in the same order as with the full
-// stencil. False when no vertex of the row can lie within r.
-__device__ __forceinline__ bool row_span(const SetHeader *hdr, const float p[3], float r, float mg, int cy, int cz,
-                                         int c0x, int c1x, int &x0, int &x1)
+// stencil. wy, wz are the cell widths 1 / cell_inv. False when no vertex of the row can lie within r.
+__device__ __forceinline__ bool row_span(const SetHeader *hdr, const float p[3], float r, float mg, float wy,
+                                         float wz, int cy, int cz, int c0x, int c1x, int &x0, int &x1)
 {
     float h2 = r * r;
     const int c[3] = {0, cy, cz};
+    const float w[3] = {0.0f, wy, wz};
 #pragma unroll
     for (int a = 1; a < 3; ++a) {
-        const float w = 1.0f / hdr->cell_inv[a];
-        const float lo = fmaf((float)c[a], w, hdr->dom_lo[a]);
-        const float d = fmaxf(fmaxf(lo - p[a], p[a] - (lo + w)) - mg, 0.0f);
+        const float lo = fmaf((float)c[a], w[a], hdr->dom_lo[a]);
+        const float d = fmaxf(fmaxf(lo - p[a], p[a] - (lo + w[a])) - mg, 0.0f);
         h2 = fmaf(-d, d, h2);
     }
     if (!(h2 >= 0.0f)) return false;

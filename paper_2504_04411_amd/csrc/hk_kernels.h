@@ -132,7 +132,8 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
                 uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres);
 void build_grid(const GridLaunch &g, hipStream_t s);
 void init_set(const InitLaunch &g, hipStream_t s);
-void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s);
+void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const uint32_t *dlen = nullptr,
+               int extra = 0);
 void launch_plan(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile, uint32_t max_cells,
                  hipStream_t s);
 void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream_t s);
