@@ -487,8 +487,9 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         // 4. one work list over the batch, the set table, one gather / test / update launch, then the
         //    radius histograms and pair counts of the batch's sets
         uint32_t *flag = reinterpret_cast<uint32_t *>(w + W.flag);
-        uint32_t *offs = reinterpret_cast<uint32_t *>(w + W.offs);
         uint32_t *ids = reinterpret_cast<uint32_t *>(w + W.ids);
+        uint32_t *tiles = reinterpret_cast<uint32_t *>(w + W.tiles);
+        launch_zero(tiles, cdiv(W.h_total, SPLIT_TILE), stream);
         SetDesc desc[MAX_BATCH];
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
@@ -503,9 +504,10 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             l.r = st.r;
             l.heavy_cost = (uint32_t)p.heavy_cost;
             l.set_slot = (uint32_t)k;
+            l.q_base = (uint32_t)W.q_off[k];
             l.flag = flag + W.q_off[k];
-            l.offs = offs + W.q_off[k];
             l.ids = ids + W.q_off[k];
+            l.tile_heavy = tiles;
             launch_cost(l, stream);
             SetDesc &d = desc[k];
             memset(&d, 0, sizeof d);
@@ -524,8 +526,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
         uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
         uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
-        launch_split(flag, offs, ids, W.h_total, reinterpret_cast<uint32_t *>(w + W.part2), heavy, light, counts,
-                     stream);
+        launch_split(flag, ids, W.h_total, tiles, heavy, light, counts, stream);
         SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
         launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
         BatchArgs a{};

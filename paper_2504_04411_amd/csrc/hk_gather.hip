@@ -602,8 +602,18 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
     const uint32_t h = cost > l.heavy_cost ? 1u : 0u;
     if (in) {
         l.flag[q] = h;
-        l.offs[q] = h;
         l.ids[q] = (l.set_slot << Q_BITS) | (uint32_t)q;
+    }
+    // heavy kernels per tile of SPLIT_TILE entries of the batch's work list (a wavefront's entries
+    // touch at most two tiles): one atomic per wavefront and tile
+    {
+        const uint32_t g = l.q_base + (uint32_t)q;
+        const uint32_t tile = g / SPLIT_TILE;
+        const uint32_t t0 = __shfl(tile, 0, WAVE);
+        const uint64_t m0 = __ballot(in && h && tile == t0), m1 = __ballot(in && h && tile != t0);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && m0) atomicAdd(&l.tile_heavy[t0], (uint32_t)__popcll(m0));
+        if (in && h && tile != t0 && (uint32_t)__popcll(m1 & ((1ull << (threadIdx.x & (WAVE - 1))) - 1ull)) == 0u)
+            atomicAdd(&l.tile_heavy[tile], (uint32_t)__popcll(m1));
     }
     // candidate tests of this iteration (every photon of the stencil is tested once): one atomic
     // per wavefront, issued at the end of the kernel
@@ -621,30 +631,54 @@ void launch_cost(const ListLaunch &l, hipStream_t s)
 
 // Stable partition of the batch's work list, heavy kernels first, in kernel order within each list
 // (the Morton order of each set, sets in batch order): the order keeps neighbouring kernels together,
-// which the gather's cache reuse depends on.
-__global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const uint32_t *offs, const uint32_t *ids,
-                                                    int64_t n, uint32_t *heavy, uint32_t *light, uint32_t *counts)
+// which the gather's cache reuse depends on. One block per tile of SPLIT_TILE entries: the heavy
+// kernels of the earlier tiles (counted by the cost kernels) give the tile's offset, a block scan
+// the ranks inside it.
+__global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const uint32_t *ids, int64_t n,
+                                                    const uint32_t *tile_heavy, uint32_t *heavy, uint32_t *light,
+                                                    uint32_t *counts)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= n) return;
-    const uint32_t o = offs[q];
-    if (flag[q])
-        heavy[o] = ids[q];
-    else
-        light[(uint32_t)q - o] = ids[q];
-    if (q == n - 1) {
-        const uint32_t nh = o + flag[q];
+    constexpr int PER = SPLIT_TILE / 256;
+    __shared__ uint32_t off_s;
+    if (threadIdx.x == 0) {
+        uint32_t o = 0;
+        for (uint32_t t = 0; t < blockIdx.x; ++t) o += tile_heavy[t];
+        off_s = o;
+    }
+    const int64_t base = (int64_t)blockIdx.x * SPLIT_TILE + (int64_t)threadIdx.x * PER;
+    uint32_t f[PER];
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        f[i] = (base + i < n) ? flag[base + i] : 0u;
+        c += f[i];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(c, &tot);         // synchronises the block (off_s is set)
+    uint32_t o = off_s + ex;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t q = base + i;
+        if (q < n) {
+            if (f[i])
+                heavy[o] = ids[q];
+            else
+                light[(uint32_t)q - o] = ids[q];
+        }
+        o += f[i];
+    }
+    if ((int64_t)(blockIdx.x + 1) * SPLIT_TILE >= n && threadIdx.x == 0) {
+        const uint32_t nh = off_s + tot;
         counts[0] = nh;
         counts[1] = (uint32_t)n - nh;
     }
 }
 
-void launch_split(uint32_t *flag, uint32_t *offs, uint32_t *ids, int64_t n, uint32_t *part, uint32_t *heavy,
+void launch_split(uint32_t *flag, uint32_t *ids, int64_t n, const uint32_t *tile_heavy, uint32_t *heavy,
                   uint32_t *light, uint32_t *counts, hipStream_t s)
 {
     if (n <= 0) return;
-    excl_scan(offs, n, part, s);
-    split_kernel<<<(int)cdiv(n, 256), 256, 0, s>>>(flag, offs, ids, n, heavy, light, counts);
+    split_kernel<<<(int)cdiv(n, SPLIT_TILE), 256, 0, s>>>(flag, ids, n, tile_heavy, heavy, light, counts);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -5,8 +5,9 @@
 //   keys      cell index of every photon (x fastest), KEY_OUTSIDE outside the grid domain
 //   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
 //             per-digit prefix over the blocks and digit totals, and a wave-ballot stable scatter
-//   permute   inverse permutation, then a coalesced read / scattered write of the photon payload
-//             into sorted order (three float4 per photon, with the photon's luminance for PPM)
+//   permute   the last sort pass writes the inverse permutation; a coalesced read / scattered write
+//             of the photon payload into sorted order (three float4 per photon, with the photon's
+//             luminance for PPM)
 //   cstart    photons per cell (wave-aggregated atomics on the sorted keys), exclusive scan:
 //             cstart[c] = first sorted position with key >= c, for c in [0, ncells]
 #include <math.h>
@@ -19,36 +20,6 @@ namespace hk {
 // ------------------------------------------------------------------------------------------------
 // scans
 // ------------------------------------------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
-
-// Exclusive scan over a 256-thread block; *total receives the block sum.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
-{
-    __shared__ uint32_t wsum[4];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t inc = wave_incl_scan(v);
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (i < w) off += wsum[i];
-        tot += wsum[i];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + inc - v;
-}
 
 // Length of a scan whose array is sized for a bound but whose live part is known on the device only
 // (the cell counts of this iteration's plan): min(len, *dlen + extra), or len when dlen is NULL.
@@ -164,10 +135,12 @@ __global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nbl
 // d plus the block's prefix within d. Items are visited in rounds of 256 consecutive keys; inside a
 // round the rank of a key among equal digits is (count in earlier rounds) + (count in lower waves)
 // + (lower lanes of the same wave, from eight ballots).
+// With `inv` (the last pass), the inverse permutation is written instead of the sorted values:
+// inv[source index] = sorted position.
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                 uint32_t *kout, uint32_t *vout, int64_t n,
                                                                 int shift, const uint32_t *offs, int nblk,
-                                                                const uint32_t *dtot)
+                                                                const uint32_t *dtot, uint32_t *inv)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
@@ -198,7 +171,11 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
             uint32_t pos = run[d] + rank;
             for (int i = 0; i < w; ++i) pos += wcnt[i][d];
             kout[pos] = key;
-            vout[pos] = vin ? vin[k] : (uint32_t)k;
+            const uint32_t src = vin ? vin[k] : (uint32_t)k;
+            if (inv)
+                inv[src] = pos;
+            else
+                vout[pos] = src;
         }
         __syncthreads();
         run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
@@ -208,17 +185,21 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
 }
 
 // Sorts n pairs whose keys use `bits` low bits. Values start as the identity permutation. Returns
-// in *kres / *vres whichever buffers hold the result.
+// in *kres whichever buffer holds the sorted keys and in *vres the one holding the sorted values
+// (sorted position -> source index), or with `inverse` the inverse permutation (source index ->
+// sorted position), which the last pass then writes instead.
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
-                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres)
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse)
 {
     const int nblk = (int)cdiv(n, RS_TILE);
     uint32_t *ki = kA, *vi = nullptr, *ko = kB, *vo = vB;
     uint32_t *vspare = vA;
     for (int shift = 0; shift < bits; shift += 8) {
+        const bool last = shift + 8 >= bits;
         rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
         rs_offsets_kernel<<<256, 256, 0, s>>>(hist, nblk, part);
-        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk, part);
+        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk, part,
+                                                      (last && inverse) ? vo : nullptr);
         uint32_t *kt = ki;
         ki = ko;
         ko = kt;
@@ -342,12 +323,6 @@ __global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const f
 }
 
 // inv[original index] = sorted position
-__global__ __launch_bounds__(256) void invert_kernel(const uint32_t *sval, int64_t n, uint32_t *inv)
-{
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q < n) inv[sval[q]] = (uint32_t)q;
-}
-
 // Reads the input photons in their own order (coalesced) and writes each to its sorted position.
 __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *pay,
                                                       int64_t ps)
@@ -390,6 +365,11 @@ __global__ __launch_bounds__(256) void cell_count_kernel(const SetHeader *hdr, c
     }
 }
 
+void launch_zero(uint32_t *p, int64_t n, hipStream_t s)
+{
+    if (n > 0) zero_kernel<<<(int)cdiv(n, 256), 256, 0, s>>>(p, n, nullptr, 0);
+}
+
 void build_grid(const GridLaunch &g, hipStream_t s)
 {
     const int64_t n = g.n;
@@ -400,10 +380,8 @@ void build_grid(const GridLaunch &g, hipStream_t s)
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
-        uint32_t *ks, *vs;
-        radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &vs);
-        uint32_t *inv = (vs == g.valA) ? g.valB : g.valA;
-        invert_kernel<<<nb, 256, 0, s>>>(vs, n, inv);
+        uint32_t *ks, *inv;
+        radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true);
         permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pstride);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
@@ -558,7 +536,7 @@ void init_set(const InitLaunch &g, hipStream_t s)
     const int nb = (int)cdiv(n, 256);
     morton_kernel<<<nb, 256, 0, s>>>(g.st.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
     uint32_t *ks, *vs;
-    radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs);
+    radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs, false);
     init_state_kernel<<<nb, 256, 0, s>>>(g.src, g.st, vs, n, g.r1);
 }
 

@@ -156,6 +156,7 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // keys per radix block
 constexpr int SCAN_TILE = 4096;                    // counters per scan block
+constexpr int SPLIT_TILE = 4096;                   // work-list entries per partition block
 // sorted payload, three float4 per photon: (x, y, z, luminance), (nx, ny, nz, dVM), (R, G, B, dVCM)
 constexpr int PAY_VEC = 3;
 
@@ -172,7 +173,7 @@ struct WsLayout {
     int64_t n_total = 0, h_total = 0, n_max = 0;
     size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
     size_t cstart = 0, pay = 0;
-    size_t flag = 0, offs = 0, ids = 0, part2 = 0, heavy = 0, light = 0, counts = 0, desc = 0;
+    size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, counts = 0, desc = 0;
     uint32_t pay_off[MAX_BATCH] = {}, cell_base[MAX_BATCH] = {}, max_cells[MAX_BATCH] = {};
     uint32_t q_off[MAX_BATCH] = {};
     size_t total = 0;
@@ -214,9 +215,8 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     W.pay = take(16 * (size_t)W.n_total * PAY_VEC + 256);     // plane stride: n_total photons
     const size_t hk = 4 * (size_t)(W.h_total + 1);
     W.flag = take(hk);
-    W.offs = take(hk);
     W.ids = take(hk);
-    W.part2 = take(4 * (size_t)(cdiv(W.h_total + 1, SCAN_TILE) + 1));
+    W.tiles = take(4 * (size_t)(cdiv(W.h_total + 1, SPLIT_TILE) + 1));
     W.heavy = take(hk);
     W.light = take(hk);
     W.counts = take(64);
@@ -328,6 +328,36 @@ __device__ __forceinline__ bool row_span(const SetHeader *hdr, const float p[3],
     x0 = (int)fminf(fmaxf(f0, (float)c0x), (float)c1x);
     x1 = (int)fminf(fmaxf(f1, (float)c0x), (float)c1x);
     return f1 >= (float)c0x && f0 <= (float)c1x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan over a 256-thread block; *total receives the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
 }
 
 // Radius histogram bin: floor(-4 log2(r / r1)) clamped to the table.

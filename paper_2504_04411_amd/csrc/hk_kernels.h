@@ -50,7 +50,9 @@ struct ListLaunch {
     const float *r;
     uint32_t heavy_cost;
     uint32_t set_slot;       // index of the set in the batch
-    uint32_t *flag, *offs, *ids;
+    uint32_t q_base;         // the set's first entry in the batch's work list
+    uint32_t *flag, *ids;
+    uint32_t *tile_heavy;    // heavy kernels per SPLIT_TILE entries of the work list (zeroed before)
 };
 
 // Everything the batched gather / test / update kernel needs besides the per-set table.
@@ -129,7 +131,7 @@ void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, con
 void launch_propose(const StateView &st, int64_t H, const float *y, float margin, hipStream_t s);
 
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
-                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres);
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse);
 void build_grid(const GridLaunch &g, hipStream_t s);
 void init_set(const InitLaunch &g, hipStream_t s);
 void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const uint32_t *dlen = nullptr,
@@ -140,8 +142,9 @@ void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream
 void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all, double alpha_f,
                   hipStream_t s);
 void launch_cost(const ListLaunch &l, hipStream_t s);
-void launch_split(uint32_t *flag, uint32_t *offs, uint32_t *ids, int64_t n, uint32_t *part, uint32_t *heavy,
+void launch_split(uint32_t *flag, uint32_t *ids, int64_t n, const uint32_t *tile_heavy, uint32_t *heavy,
                   uint32_t *light, uint32_t *counts, hipStream_t s);
+void launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   // bytes: multiple of 4
 void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
 void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s);
