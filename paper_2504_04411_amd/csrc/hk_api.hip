@@ -39,7 +39,7 @@ int fail(int code, const char *fmt, ...)
 constexpr int MAX_SETS = 256;
 constexpr int64_t MAX_KERNELS = ((int64_t)1 << Q_BITS) - 1;       // per set
 constexpr int64_t MAX_STORED = ((int64_t)1 << 27) - 1;            // per set and iteration
-constexpr int64_t MAX_BATCH_PHOTONS = ((int64_t)1 << 28) - 1;     // per gather launch (32-bit offsets)
+constexpr int64_t MAX_BATCH_PHOTONS = ((int64_t)1 << 27) - 1;     // per gather launch (32-bit offsets)
 
 struct SetInfo {
     bool init = false;
@@ -478,6 +478,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             g.cstart = ws_cstart + W.cell_base[k];
             g.pay = ws_pay + W.pay_off[k];
             g.pstride = W.n_total;
+            g.pay_off = W.pay_off[k];
             g.ncells_bound = W.max_cells[k];
             build_grid(g, stream);
         }
@@ -1009,6 +1010,7 @@ extern "C" int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_ph
     g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
     g.pay = reinterpret_cast<float4 *>(w + W.pay);
     g.pstride = W.n_total;
+    g.pay_off = 0;
     g.ncells_bound = W.max_cells[0];
     build_grid(g, stream);
     launch_features(st, S.H, g.cstart, g.pay, g.pstride, nrm_test, ctx->p.normal_cos_min, it_code, feat, counts,

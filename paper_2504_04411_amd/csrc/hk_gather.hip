@@ -127,13 +127,13 @@ struct Cand {
 };
 
 template <bool NRM, bool VCM>
-__device__ __forceinline__ Cand load_cand(uint32_t pi, const float4 *rA, const float4 *rB, const float4 *rC)
+__device__ __forceinline__ Cand load_cand(uint32_t pi, const float4 *rA, const float4 *rBC)
 {
     Cand P;
     P.a = ld4(rA, pi);
-    P.f = ld4(rC, pi);
+    P.f = ld4(rBC, 2u * pi + 1u);
     P.b = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-    if (NRM || VCM) P.b = ld4(rB, pi);
+    if (NRM || VCM) P.b = ld4(rBC, 2u * pi);
     return P;
 }
 
@@ -216,8 +216,8 @@ __device__ __forceinline__ uint32_t ring(uint32_t i)
 
 template <int G, bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool flush, int j, int base,
-                                           const Query &K, float cos_min, const float4 *rA, const float4 *rB,
-                                           const float4 *rC, Lds<CH> &L, int lane, Acc &c)
+                                           const Query &K, float cos_min, const float4 *rA, const float4 *rBC,
+                                           Lds<CH> &L, int lane, Acc &c)
 {
     __syncthreads();
     const uint32_t cap = (qlen < (uint32_t)(DRAIN * G)) ? qlen : (uint32_t)(DRAIN * G);
@@ -227,7 +227,7 @@ __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool 
 #pragma unroll
     for (int i = 0; i < DRAIN; ++i)
         if (k + (uint32_t)(i * G) < n)
-            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k + (uint32_t)(i * G))], rA, rB, rC);
+            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k + (uint32_t)(i * G))], rA, rBC);
 #pragma unroll
     for (int i = 0; i < DRAIN; ++i)
         if (k + (uint32_t)(i * G) < n) accumulate<NRM, VCM, CH>(P[i], K, cos_min, L, lane, c);
@@ -253,7 +253,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const double *fctab = reinterpret_cast<const double *>(D.state + D.fctab);
     const float *lbtab = reinterpret_cast<const float *>(D.state + D.lbtab);
     // payload planes at a wave-uniform base; photon indices are global (set offset added per row)
-    const float4 *rA = A.pay, *rB = A.pay + A.pstride, *rC = A.pay + 2 * (size_t)A.pstride;
+    // payload: the (position, luminance) plane, then (normal, dVM), (flux, dVCM) pairs per photon
+    const float4 *rA = A.pay, *rBC = A.pay + A.pstride;
     const uint32_t *cstart = A.cstart + D.cell_base;
     const int iter = active ? hdr->iter : 1;
     const float Jf = active ? hdr->Jf : 1.0f;
@@ -363,7 +364,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                 if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
                 qlen += (uint32_t)__popcll(m & gmask);
                 if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
-                    drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+                    drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rBC, L, lane, c);
             }
         }
     }
@@ -394,7 +395,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     for (int cc = 0; cc < 6; ++cc) tv[cc] = lead ? fslot(SL_TAU + cc)[q] : 0.0f;
 
     while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rB, rC, L, lane, c);
+        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rBC, L, lane, c);
     __syncthreads();
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in

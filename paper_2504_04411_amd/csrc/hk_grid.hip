@@ -6,8 +6,9 @@
 //   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
 //             per-digit prefix over the blocks and digit totals, and a wave-ballot stable scatter
 //   permute   the last sort pass writes the inverse permutation; a coalesced read / scattered write
-//             of the photon payload into sorted order (three float4 per photon, with the photon's
-//             luminance for PPM)
+//             of the photon payload into sorted order: a plane of (position, luminance) float4s for
+//             the candidate tests, then one 32-byte record per photon of (normal, dVM) and (flux,
+//             dVCM), which the accumulation reads together
 //   cstart    photons per cell (wave-aggregated atomics on the sorted keys), exclusive scan:
 //             cstart[c] = first sorted position with key >= c, for c in [0, ncells]
 #include <math.h>
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const f
 // inv[original index] = sorted position
 // Reads the input photons in their own order (coalesced) and writes each to its sorted position.
 __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *pay,
-                                                      int64_t ps)
+                                                      float4 *pairs)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
@@ -334,11 +335,12 @@ __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, 
     const float dvcm = src.mis[0] ? src.mis[0][j] : 0.0f;
     const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
     pay[q] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
+    float4 *bc = pairs + 2 * (int64_t)q;
     if (src.nrm[0])
-        pay[ps + q] = make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm);
+        bc[0] = make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm);
     else
-        pay[ps + q] = make_float4(0.0f, 0.0f, 1.0f, dvm);
-    pay[2 * ps + q] = make_float4(R, G, B, dvcm);
+        bc[0] = make_float4(0.0f, 0.0f, 1.0f, dvm);
+    bc[1] = make_float4(R, G, B, dvcm);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t n, const uint32_t *dlen, int extra)
@@ -382,7 +384,8 @@ void build_grid(const GridLaunch &g, hipStream_t s)
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
         uint32_t *ks, *inv;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true);
-        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pstride);
+        // the set's pairs: plane base + pstride + 2 pay_off, with plane base = g.pay - pay_off
+        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pay + g.pstride + g.pay_off);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
     excl_scan(g.cstart, nc, g.part3, s, &g.hdr->ncells, 1);

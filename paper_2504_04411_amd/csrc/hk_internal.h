@@ -157,7 +157,8 @@ constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // keys per radix block
 constexpr int SCAN_TILE = 4096;                    // counters per scan block
 constexpr int SPLIT_TILE = 4096;                   // work-list entries per partition block
-// sorted payload, three float4 per photon: (x, y, z, luminance), (nx, ny, nz, dVM), (R, G, B, dVCM)
+// sorted payload, three float4 per photon: a plane of (x, y, z, luminance), then per photon the pair
+// (nx, ny, nz, dVM), (R, G, B, dVCM)
 constexpr int PAY_VEC = 3;
 
 inline uint32_t max_cells_for(int64_t n_photons)

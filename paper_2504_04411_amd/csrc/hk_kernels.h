@@ -26,8 +26,9 @@ struct GridLaunch {
     PhotonSrc src;
     int64_t n;
     uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *part3, *cstart;
-    float4 *pay;
-    int64_t pstride;
+    float4 *pay;             // the set's first (position, luminance) entry: plane base + pay_off
+    int64_t pstride;         // entries per plane: the (normal, flux) pairs start at plane base + pstride
+    int64_t pay_off;         // the set's first photon in the batch's payload
     uint32_t ncells_bound;   // cells of the plan never exceed this (workspace capacity)
 };
 

@@ -365,7 +365,7 @@ __global__ __launch_bounds__(64 * FEAT_WAVES) void features_kernel(StateView st,
                         const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         if (!(d2 < R2[0])) continue;
                         if (nrm_test) {
-                            const float4 bn = pay[pstride + j];
+                            const float4 bn = pay[pstride + 2 * (int64_t)j];
                             const float cs = fmaf(nv[2], bn.z, fmaf(nv[1], bn.y, nv[0] * bn.x));
                             if (!(cs >= cos_min)) continue;
                         }
