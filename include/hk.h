@@ -141,7 +141,7 @@ int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, c
 
 /* Runs one iteration (steps 1-6 above) for each of the n_sets (1..256, distinct) sets; ph[s] holds
  * set s's light vertices, state[s] its state, set_ids[s] its id. Each set's grid is built by its own
- * launches; the gather, test and update of up to 64 sets (2^28 - 1 stored light vertices in total)
+ * launches; the gather, test and update of up to 64 sets (2^27 - 1 stored light vertices in total)
  * run as ONE launch over a work list spanning those sets, so many small, uneven sets fill the GPU
  * together. Sets with and without the normal test go to separate launches. `workspace` (device,
  * workspace_bytes long) must hold hk_workspace_bytes_batch over the sets (HK_E_SMALL_BUFFER
