@@ -503,6 +503,9 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             l.cstart = ws_cstart + W.cell_base[k];
             for (int a = 0; a < 3; ++a) l.kp[a] = st.pos[a];
             l.r = st.r;
+            l.cand = st.cand;
+            l.dec = st.dec;
+            l.k2 = p.k * p.k;
             l.heavy_cost = (uint32_t)p.heavy_cost;
             l.set_slot = (uint32_t)k;
             l.q_base = (uint32_t)W.q_off[k];

@@ -296,6 +296,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     for (int g = 0; g < NG * CH; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
     uint32_t qlen = 0, head = 0;
+    uint32_t ncand = 0;                           // candidate tests of this kernel (all row batches)
 
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
     const bool any = active && stencil(hdr, K.p, r, c0, c1);
@@ -325,6 +326,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         L.re[lane] = inc;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
+        ncand += total;
         // Per-lane cursor over the concatenated rows: photon index = virtual index + delta of its row.
         // Loads are issued U steps at a time (U independent 16-byte loads in flight per lane), then
         // the U candidates are tested from registers; those inside the disk are queued.
@@ -484,6 +486,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         uslot(SL_NSEEN)[q] = shrink ? 0u : seen;
         uslot(SL_CNT)[q] = cnt_q;
         uslot(SL_DEC)[q] = shrink ? 1u : 0u;
+        uslot(SL_CAND)[q] = ncand;
         dslot(SL_F)[q] = seen > 0u ? F : (double)NAN;
         dslot(SL_FC)[q] = Fc;
     }
@@ -587,7 +590,13 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
     const float p[3] = {l.kp[0][q], l.kp[1][q], l.kp[2][q]};
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
     uint32_t cost = 0;
-    if (in && stencil(l.hdr, p, l.r[q], c0, c1)) {
+    // the set's first iteration (the plan has advanced the count to 1) counts the stencil's photons;
+    // later ones take the estimate, decided on the device so that a captured graph does the same
+    if (l.hdr->iter > 1) {
+        // the last iteration's candidate tests, scaled by the area ratio k^2 where the radius shrank
+        const uint32_t prev = l.cand[q];
+        cost = l.dec[q] ? (uint32_t)((float)prev * l.k2) : prev;
+    } else if (in && stencil(l.hdr, p, l.r[q], c0, c1)) {
         const uint32_t dimx = (uint32_t)l.hdr->dims[0], dimy = (uint32_t)l.hdr->dims[1];
         const float rq = l.r[q];
         const float mg = fmaf(rq, 1e-4f, l.hdr->margin_abs);
@@ -616,12 +625,6 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
         if (in && h && tile != t0 && (uint32_t)__popcll(m1 & ((1ull << (threadIdx.x & (WAVE - 1))) - 1ull)) == 0u)
             atomicAdd(&l.tile_heavy[tile], (uint32_t)__popcll(m1));
     }
-    // candidate tests of this iteration (every photon of the stencil is tested once): one atomic
-    // per wavefront, issued at the end of the kernel
-    unsigned long long v = cost;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && v) atomicAdd(&l.hdr->n_cand, v);
 }
 
 void launch_cost(const ListLaunch &l, hipStream_t s)
@@ -694,7 +697,7 @@ constexpr int TALLY_PER_BLOCK = 4096;
 __global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const uint32_t *ids, int64_t n)
 {
     __shared__ uint32_t hist[RHIST_BINS];
-    __shared__ unsigned long long pairs;
+    __shared__ unsigned long long pairs, cands;
     const int64_t b0 = (int64_t)blockIdx.x * TALLY_PER_BLOCK;
     const int64_t b1 = min(n, b0 + (int64_t)TALLY_PER_BLOCK);
     const uint32_t set0 = ids[b0] >> Q_BITS;
@@ -702,9 +705,9 @@ __global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const u
     SetHeader *h0 = reinterpret_cast<SetHeader *>(D0.state + D0.hdr);
     const float r1_0 = h0->r1;
     if (threadIdx.x < RHIST_BINS) hist[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) pairs = 0ull;
+    if (threadIdx.x == 0) pairs = cands = 0ull;
     __syncthreads();
-    unsigned long long acc = 0;
+    unsigned long long acc = 0, accc = 0;
     for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) {
         const uint32_t id = ids[e];
         const uint32_t set = id >> Q_BITS, q = id & ((1u << Q_BITS) - 1u);
@@ -712,6 +715,7 @@ __global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const u
             const char *arr = D0.state + D0.arr;
             const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D0.stride)[q];
             acc += reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D0.stride)[q];
+            accc += reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CAND * D0.stride)[q];
             atomicAdd(&hist[radius_bin(r, r1_0)], 1u);
         } else {
             const SetDesc D = desc[set];
@@ -719,16 +723,23 @@ __global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const u
             const char *arr = D.state + D.arr;
             const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D.stride)[q];
             const uint32_t c = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D.stride)[q];
+            const uint32_t cc = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CAND * D.stride)[q];
             atomicAdd(&h->rhist[radius_bin(r, h->r1)], 1u);
             if (c) atomicAdd(&h->n_pairs, (unsigned long long)c);
+            if (cc) atomicAdd(&h->n_cand, (unsigned long long)cc);
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o, WAVE);
+        accc += __shfl_xor(accc, o, WAVE);
+    }
     if ((threadIdx.x & (WAVE - 1)) == 0 && acc) atomicAdd(&pairs, acc);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && accc) atomicAdd(&cands, accc);
     __syncthreads();
     if (threadIdx.x < RHIST_BINS && hist[threadIdx.x]) atomicAdd(&h0->rhist[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0 && pairs) atomicAdd(&h0->n_pairs, pairs);
+    if (threadIdx.x == 0 && cands) atomicAdd(&h0->n_cand, cands);
 }
 
 void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s)

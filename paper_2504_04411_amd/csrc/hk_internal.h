@@ -54,7 +54,7 @@ struct SetHeader {
 enum Slot : int {
     SL_POS = 0, SL_NRM = 3, SL_U = 6, SL_V = 9, SL_R = 12, SL_T = 13, SL_NSEEN = 14, SL_ORIG = 15, SL_CNT = 16,
     SL_DEC = 17, SL_TAU = 18, SL_F = SL_TAU + 6, SL_FC = SL_F + 2, SL_CB = SL_FC + 2, SL_CDVCM = SL_CB + 3,
-    SL_CDVM = SL_CDVCM + 1, SL_SQ = SL_CDVM + 1
+    SL_CDVM = SL_CDVCM + 1, SL_CAND = SL_CDVM + 1, SL_SQ = SL_CAND + 1
 };
 
 constexpr int slot_count(int nch) { return SL_SQ + NSQ * nch; }
@@ -98,6 +98,7 @@ struct StateView {
     float *pos[3], *nrm[3], *u[3], *v[3];
     float *r;
     uint32_t *t, *nseen, *orig, *cnt, *dec;
+    uint32_t *cand;      // candidate tests of the last iteration (the next work list's cost estimate)
     float *sq0;          // group sums: array k at sq0 + k * astride, NSQ * nch arrays
     int nch;             // test channels
     float *tau0;         // estimate: array c at tau0 + c * astride
@@ -129,6 +130,7 @@ inline StateView make_view(void *base, const Layout &L)
     s.orig = u(SL_ORIG);
     s.cnt = u(SL_CNT);
     s.dec = u(SL_DEC);
+    s.cand = u(SL_CAND);
     s.sq0 = f(SL_SQ);
     s.nch = L.nch;
     s.tau0 = f(SL_TAU);

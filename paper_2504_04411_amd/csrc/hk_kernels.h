@@ -49,6 +49,8 @@ struct ListLaunch {
     const uint32_t *cstart;
     const float *kp[3];
     const float *r;
+    const uint32_t *cand, *dec;  // the last iteration's candidate tests and shrink decisions
+    float k2;                    // shrink factor squared (area ratio of a shrink)
     uint32_t heavy_cost;
     uint32_t set_slot;       // index of the set in the batch
     uint32_t q_base;         // the set's first entry in the batch's work list

@@ -190,7 +190,7 @@ def test_autotune_keeps_state_and_picks_a_candidate():
     print(f"  chosen: {t}", flush=True)
     assert torch.equal(before, est.states[0])
     assert t["cell_scale"] in [np.float32(c) for c in (0.7, 1.0, 1.4)]
-    assert t["lanes_light"] in (4, 8, 16) and t["heavy_cost"] in (1024, 4096, 16384)
+    assert t["lanes_light"] in (4, 8, 16) and t["heavy_cost"] in (1024, 2048, 4096, 16384)
     assert est.tuning() == t
     assert est.stats(0)["iterations"] == 1
 
