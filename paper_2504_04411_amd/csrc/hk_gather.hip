@@ -115,9 +115,20 @@ struct Query {
     float r2, inv_eta, wc, cb[3];
 };
 
+// Kahan's compensated sum: c carries the negated rounding error of the running sum s, so s - c tracks
+// the exact sum to within about 2u of its magnitude. Used for the flux sums, which feed the estimate
+// only; the test's group sums keep the exact-error pairs of acc2.
+__device__ __forceinline__ void kahan(float &s, float &c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
 // Accumulators of one lane.
 struct Acc {
-    float fR, cR, fG, cG, fB, cB;
+    float fR, cR, fG, cG, fB, cB;         // flux sums with their Kahan compensations
     uint32_t cnt;
 };
 
@@ -193,9 +204,9 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
             L.slot[ch * NG + g][lane] = sv;
         }
     }
-    acc2(c.fR, c.cR, wR);
-    acc2(c.fG, c.cG, wG);
-    acc2(c.fB, c.cB, wB);
+    kahan(c.fR, c.cR, wR);
+    kahan(c.fG, c.cG, wG);
+    kahan(c.fB, c.cB, wB);
     c.cnt += ok ? 1u : 0u;
 }
 
@@ -402,7 +413,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
     // lane order; the flux pairs are folded across the kernel's lanes by a butterfly.
-    float fR = c.fR, xR = c.cR, fG = c.fG, xG = c.cG, fB = c.fB, xB = c.cB;
+    float fR = c.fR, xR = -c.cR, fG = c.fG, xG = -c.cG, fB = c.fB, xB = -c.cB;   // pairs s + x
     group_sum_pair<G>(fR, xR);
     group_sum_pair<G>(fG, xG);
     group_sum_pair<G>(fB, xB);
