@@ -270,7 +270,6 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const int iter = active ? hdr->iter : 1;
     const float Jf = active ? hdr->Jf : 1.0f;
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
-    const uint64_t below = (j == 0) ? 0ull : ((~0ull >> (64 - j)) << base);
 
     Query K;
     for (int a = 0; a < 3; ++a) {
@@ -350,8 +349,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             uint32_t pis[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                pis[u] = 0xFFFFFFFFu;
-                a[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                pis[u] = 0u;
+                a[u] = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);   // no candidate: never inside
                 if (vi < total) {
                     while (vi >= row_end) {
                         ++cur;
@@ -365,17 +364,16 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             }
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                bool in = false;
-                if (pis[u] != 0xFFFFFFFFu) {
-                    const float dx = K.p[0] - a[u].x, dy = K.p[1] - a[u].y, dz = K.p[2] - a[u].z;
-                    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    in = d2 < K.r2;
-                }
-                // queue the in-disk photons of this step in lane order
-                const uint64_t m = __ballot(in);
-                const uint32_t before = (uint32_t)__popcll(m & below);
+                const float dx = K.p[0] - a[u].x, dy = K.p[1] - a[u].y, dz = K.p[2] - a[u].z;
+                const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const bool in = d2 < K.r2;
+                // queue the in-disk photons of this step in lane order: the kernel's lanes of the
+                // ballot, counted below this lane and in all
+                const uint64_t mk = __ballot(in) & gmask;
+                const uint32_t before =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
                 if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
-                qlen += (uint32_t)__popcll(m & gmask);
+                qlen += (uint32_t)__popcll(mk);
                 if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
                     drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rBC, L, lane, c);
             }
