@@ -410,21 +410,45 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     __syncthreads();
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
-    // lane order; the flux pairs are folded across the kernel's lanes by a butterfly.
+    // lane order (a whole-wavefront kernel: four lanes per group, 16 partials each, then a
+    // butterfly); the flux pairs are folded across the kernel's lanes by a butterfly.
     float fR = c.fR, xR = -c.cR, fG = c.fG, xG = -c.cG, fB = c.fB, xB = -c.cB;   // pairs s + x
     group_sum_pair<G>(fR, xR);
     group_sum_pair<G>(fG, xG);
     group_sum_pair<G>(fB, xB);
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        const int col = j + k * G;
+    if constexpr (G == WAVE && COLS <= 16) {
+        // the retained sums sit in lanes 0..COLS-1 (zero elsewhere) and enter once
+        const int col = j & 15, sub = j >> 4;
         if (col < COLS) {
-            for (int l = 0; l < G; ++l) {
-                const float4 x = L.slot[col][base + l];
-                acc2(S[k], cS[k], x.x);
-                cS[k] += x.y;
-                acc2(Q[k], cQ[k], x.z);
-                cQ[k] += x.w;
+            for (int l = 0; l < 16; ++l) {
+                const float4 x = L.slot[col][base + sub * 16 + l];
+                acc2(S[0], cS[0], x.x);
+                cS[0] += x.y;
+                acc2(Q[0], cQ[0], x.z);
+                cQ[0] += x.w;
+            }
+        }
+#pragma unroll
+        for (int o = 16; o < WAVE; o <<= 1) {
+            const float s2 = __shfl_xor(S[0], o, WAVE), c2 = __shfl_xor(cS[0], o, WAVE);
+            const float q2 = __shfl_xor(Q[0], o, WAVE), d2 = __shfl_xor(cQ[0], o, WAVE);
+            cS[0] = cS[0] + c2;
+            acc2(S[0], cS[0], s2);
+            cQ[0] = cQ[0] + d2;
+            acc2(Q[0], cQ[0], q2);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const int col = j + k * G;
+            if (col < COLS) {
+                for (int l = 0; l < G; ++l) {
+                    const float4 x = L.slot[col][base + l];
+                    acc2(S[k], cS[k], x.x);
+                    cS[k] += x.y;
+                    acc2(Q[k], cQ[k], x.z);
+                    cQ[k] += x.w;
+                }
             }
         }
     }
