@@ -3,29 +3,32 @@
 //
 // Work decomposition: G lanes of a wavefront serve one kernel (hit point). The kernel's grid
 // stencil (cells overlapping the box [x - r, x + r], grown by a rounding margin) is a list of rows
-// of cells; with x fastest each row is a contiguous range of the sorted photon payload. The G lanes
-// walk the concatenated rows G photons at a time (coalesced 16-byte loads), test their photon
-// against the disk and accumulate into lane-private compensated sums kept in LDS. At the end the
-// G partial results are combined in a fixed order (deterministic) and the kernel's epilogue runs.
+// of cells; with x fastest each row is a contiguous range of the sorted photon payload, clipped to
+// the x-range that can reach the disk. The G lanes walk the concatenated rows G photons at a time
+// (coalesced 16-byte loads, eight in flight per lane), test their photon against the disk and
+// accumulate into lane-private compensated sums kept in LDS. At the end the G partial results are
+// combined in a fixed order (deterministic) and the kernel's epilogue runs.
 //
 // The test and the accumulation are decoupled: each step tests G candidates (one per lane), the
-// in-disk ones are queued in LDS (lane order) and later accumulated G at a time by the kernel's G
-// lanes together, so the accumulation runs with every lane busy instead of only the third of lanes
-// whose candidate fell inside the disk.
+// in-disk ones are queued in LDS (stream order) and later accumulated up to 2G at a time by the
+// kernel's G lanes together, so the accumulation runs with every lane busy instead of only the
+// third of lanes whose candidate fell inside the disk. Lane j always takes the in-disk photons at
+// stream positions congruent to j mod G, so the sums do not depend on the other kernels of the wave.
 //
-// Light kernels share a wave (8 lanes each by default); kernels whose stencil holds more than
-// `heavy_cost` photons get a whole wave and are listed first, so the longest work starts first. The
-// list is rebuilt every iteration from the grid (cost = photons in the stencil) and spans every set
-// of the batch: one launch serves many hit-point sets of uneven size. Each lane reads its set's
-// record (state buffer, payload and cell-start offsets) from a small device table, and everything
-// that changes between iterations (iteration index, J, lower bound) comes from the set's state, so
-// the launch can be replayed from a captured graph.
+// Light kernels share a wave (16 lanes each as tuned); kernels whose expected candidate count
+// exceeds `heavy_cost` get a whole wave and are listed first, so the longest work starts first. The
+// list is rebuilt every iteration (cost = the stencil's photons in a set's first iteration, then the
+// candidates tested the iteration before) and spans every set of the batch: one launch serves many
+// hit-point sets of uneven size. Each lane reads its set's record (state buffer, payload and
+// cell-start offsets) from a small device table, and everything that changes between iterations
+// (iteration index, J, lower bound) comes from the set's state, so the launch can be replayed from a
+// captured graph.
 //
 // Per pair inside the disk (Sec. 3.2, Sec. 5.1):
 //   y = (<x - x*, u>, <x - x*, v>)             (Eq. map-function)
 //   g = annulus (2 d2 >= r2) x sector (60 degree wedges from +u)
 //   S_g += psi, Q_g += psi^2                  (compensated float32 pairs, TwoSum / fma product)
-//   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1)
+//   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1), Kahan-compensated
 // Epilogue per kernel: retained sums (Sec. 5.1), F in float64 (Eq. f-statistic) against the
 // tabulated critical value for m = sum of J over the kept iterations, estimate update
 // (Eq. progressive-VCM-estimator) with this iteration's radius, then Eq. radiusupdate.
