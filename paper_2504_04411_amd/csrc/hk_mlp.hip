@@ -229,13 +229,29 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpView M, const uint16_t
 }
 
 // grad[p] = sum over workgroups of part[wg][p], in workgroup order (float64), p < MLP_P + 1.
+// Sum of the workgroups' partial gradients in float64: a block serves 32 parameters with 8 slices
+// of the workgroups each (coalesced rows of 32 partials), the slices then added in slice order, so
+// the result does not depend on scheduling.
+constexpr int RED_PARAMS = 32, RED_SLICES = 8;
+
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *part, int nwg, float *grad)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p > MLP_P) return;
+    __shared__ double acc_s[RED_SLICES][RED_PARAMS];
+    const int pl = threadIdx.x % RED_PARAMS, sl = threadIdx.x / RED_PARAMS;
+    const int p = blockIdx.x * RED_PARAMS + pl;
+    const int per = (nwg + RED_SLICES - 1) / RED_SLICES;
+    const int b0 = sl * per, b1 = min(nwg, b0 + per);
     double acc = 0.0;
-    for (int b = 0; b < nwg; ++b) acc += (double)part[(size_t)b * MLP_PP + p];
-    grad[p] = (float)acc;
+    if (p <= MLP_P)
+        for (int b = b0; b < b1; ++b) acc += (double)part[(size_t)b * MLP_PP + p];
+    acc_s[sl][pl] = acc;
+    __syncthreads();
+    if (sl == 0 && p <= MLP_P) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < RED_SLICES; ++k) t += acc_s[k][pl];
+        grad[p] = (float)t;
+    }
 }
 
 __device__ __forceinline__ void refresh_bf16(const MlpView &M, int p)
@@ -310,7 +326,7 @@ void launch_mlp_grad(const MlpView &M, const uint16_t *feat, const float *label,
 {
     const int nwg = mlp_grid(n);
     mlp_grad_kernel<<<nwg, 256, 0, s>>>(M, feat, label, n, 1.0f / (float)n, part);
-    mlp_reduce_kernel<<<(int)cdiv(MLP_P + 1, 256), 256, 0, s>>>(part, nwg, grad);
+    mlp_reduce_kernel<<<(int)cdiv(MLP_P + 1, RED_PARAMS), 256, 0, s>>>(part, nwg, grad);
 }
 
 void launch_mlp_adam(const MlpView &M, const float *grad, float lr, hipStream_t s)

@@ -200,14 +200,15 @@ def compare(est: Estimator, net: Network, w, batches, truth: torch.Tensor, margi
 
 
 def choose_margin(est: Estimator, net: Network, w, batches, truth, margins, set_id: int = 0):
-    """The margin whose learned run reaches the plain run's final MSE soonest (GPU time) on a
-    validation scene; ties and misses fall back to the lowest final MSE."""
+    """The margin whose learned run reaches the plain run's final MSE in the fewest iterations on a
+    validation scene (a deterministic criterion: timings would make the choice vary from run to
+    run); ties and misses fall back to the lowest final MSE."""
     plain = _run(est, set_id, w, batches, truth)
     best, key_best, runs = None, None, {}
     for m in margins:
         s = summarize(plain, _run(est, set_id, w, batches, truth, net, m))
         runs[m] = s
-        key = (s["learned_ms_to_plain_final_mse"] is None, s["learned_ms_to_plain_final_mse"] or 0.0,
+        key = (s["learned_iters_to_plain_final_mse"] is None, s["learned_iters_to_plain_final_mse"] or 0,
                s["learned_final_mse"])
         if key_best is None or key < key_best:
             best, key_best = m, key
