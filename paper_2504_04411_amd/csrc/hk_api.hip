@@ -530,7 +530,8 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
         uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
         uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
-        launch_split(flag, ids, W.h_total, tiles, heavy, light, counts, stream);
+        launch_split(flag, ids, W.h_total, (uint32_t)p.heavy_cost, tiles, heavy, light,
+                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, stream);
         SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
         launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
         BatchArgs a{};

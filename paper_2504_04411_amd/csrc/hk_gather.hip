@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
     }
     const uint32_t h = cost > l.heavy_cost ? 1u : 0u;
     if (in) {
-        l.flag[q] = h;
+        l.flag[q] = cost;
         l.ids[q] = (l.set_slot << Q_BITS) | (uint32_t)q;
     }
     // heavy kernels per tile of SPLIT_TILE entries of the batch's work list (a wavefront's entries
@@ -674,9 +674,9 @@ void launch_cost(const ListLaunch &l, hipStream_t s)
 // which the gather's cache reuse depends on. One block per tile of SPLIT_TILE entries: the heavy
 // kernels of the earlier tiles (counted by the cost kernels) give the tile's offset, a block scan
 // the ranks inside it.
-__global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const uint32_t *ids, int64_t n,
-                                                    const uint32_t *tile_heavy, uint32_t *heavy, uint32_t *light,
-                                                    uint32_t *counts)
+__global__ __launch_bounds__(256) void split_kernel(const uint32_t *cost, const uint32_t *ids, int64_t n,
+                                                    uint32_t heavy_cost, const uint32_t *tile_heavy, uint32_t *heavy,
+                                                    uint32_t *light, uint32_t *lcost, uint32_t *counts)
 {
     constexpr int PER = SPLIT_TILE / 256;
     __shared__ uint32_t off_s;
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const 
     uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        f[i] = (base + i < n) ? flag[base + i] : 0u;
+        f[i] = (base + i < n && cost[base + i] > heavy_cost) ? 1u : 0u;
         c += f[i];
     }
     uint32_t tot;
@@ -700,10 +700,12 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const 
     for (int i = 0; i < PER; ++i) {
         const int64_t q = base + i;
         if (q < n) {
-            if (f[i])
+            if (f[i]) {
                 heavy[o] = ids[q];
-            else
+            } else {
                 light[(uint32_t)q - o] = ids[q];
+                lcost[(uint32_t)q - o] = cost[q];
+            }
         }
         o += f[i];
     }
@@ -714,11 +716,46 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *flag, const 
     }
 }
 
-void launch_split(uint32_t *flag, uint32_t *ids, int64_t n, const uint32_t *tile_heavy, uint32_t *heavy,
-                  uint32_t *light, uint32_t *counts, hipStream_t s)
+// The light list in runs of LSORT entries sorted by expected cost (ties by position): a wavefront's
+// kernels then carry similar work, while a run (a compact patch of the Morton order, as many
+// wavefronts as an XCD chunk) keeps its cache locality. Bitonic sort of (cost, position) keys.
+constexpr int LSORT = 256;
+
+__global__ __launch_bounds__(LSORT) void light_sort_kernel(uint32_t *light, const uint32_t *lcost,
+                                                           const uint32_t *counts)
+{
+    __shared__ uint64_t key[LSORT];
+    const uint32_t n = counts[1];
+    const uint32_t b0 = blockIdx.x * LSORT;
+    if (b0 >= n) return;
+    const int t = threadIdx.x;
+    const uint32_t i = b0 + (uint32_t)t;
+    key[t] = (i < n) ? (((uint64_t)lcost[i] << 40) | ((uint64_t)t << 32) | light[i]) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= LSORT; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            const int p = t ^ jj;
+            if (p > t) {
+                const uint64_t a = key[t], b = key[p];
+                const bool up = (t & k) == 0;
+                if ((a > b) == up) {
+                    key[t] = b;
+                    key[p] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (i < n) light[i] = (uint32_t)key[t];
+}
+
+void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost, const uint32_t *tile_heavy,
+                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, hipStream_t s)
 {
     if (n <= 0) return;
-    split_kernel<<<(int)cdiv(n, SPLIT_TILE), 256, 0, s>>>(flag, ids, n, tile_heavy, heavy, light, counts);
+    split_kernel<<<(int)cdiv(n, SPLIT_TILE), 256, 0, s>>>(cost, ids, n, heavy_cost, tile_heavy, heavy, light, lcost,
+                                                          counts);
+    light_sort_kernel<<<(int)cdiv(n, LSORT), LSORT, 0, s>>>(light, lcost, counts);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -176,7 +176,7 @@ struct WsLayout {
     int64_t n_total = 0, h_total = 0, n_max = 0;
     size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
     size_t cstart = 0, pay = 0;
-    size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, counts = 0, desc = 0;
+    size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, lcost = 0, counts = 0, desc = 0;
     uint32_t pay_off[MAX_BATCH] = {}, cell_base[MAX_BATCH] = {}, max_cells[MAX_BATCH] = {};
     uint32_t q_off[MAX_BATCH] = {};
     size_t total = 0;
@@ -222,6 +222,7 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     W.tiles = take(4 * (size_t)(cdiv(W.h_total + 1, SPLIT_TILE) + 1));
     W.heavy = take(hk);
     W.light = take(hk);
+    W.lcost = take(hk);
     W.counts = take(64);
     W.desc = take(sizeof(SetDesc) * MAX_BATCH);
     W.total = off;

@@ -54,7 +54,7 @@ struct ListLaunch {
     uint32_t heavy_cost;
     uint32_t set_slot;       // index of the set in the batch
     uint32_t q_base;         // the set's first entry in the batch's work list
-    uint32_t *flag, *ids;
+    uint32_t *flag, *ids;        // flag: each kernel's expected cost
     uint32_t *tile_heavy;    // heavy kernels per SPLIT_TILE entries of the work list (zeroed before)
 };
 
@@ -145,8 +145,8 @@ void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream
 void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all, double alpha_f,
                   hipStream_t s);
 void launch_cost(const ListLaunch &l, hipStream_t s);
-void launch_split(uint32_t *flag, uint32_t *ids, int64_t n, const uint32_t *tile_heavy, uint32_t *heavy,
-                  uint32_t *light, uint32_t *counts, hipStream_t s);
+void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost, const uint32_t *tile_heavy,
+                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, hipStream_t s);
 void launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   // bytes: multiple of 4
 void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
