@@ -548,7 +548,9 @@ __global__ __launch_bounds__(WAVE) void gather_update_kernel(BatchArgs A)
     constexpr uint32_t KPW_L = WAVE / GL;     // light kernels per wave
     constexpr uint32_t KPW_H = WAVE / GH;     // heavy kernels per wave
     const uint32_t n_heavy = A.counts[0], n_light = A.counts[1];
-    const uint32_t items_h = (n_heavy + KPW_H - 1) / KPW_H;
+    // heavy items padded to whole XCD chunks, so that each chunk of light items is one cost-sorted
+    // run of the light list (a compact patch)
+    const uint32_t items_h = ((n_heavy + KPW_H - 1) / KPW_H + XCD_CHUNK - 1) / XCD_CHUNK * XCD_CHUNK;
     const uint32_t n_items = items_h + (n_light + KPW_L - 1) / KPW_L;
     // Workgroups are dealt to the 8 XCDs round-robin. Chunk k of XCD_CHUNK consecutive items (a
     // compact patch along the Morton order) goes to XCD k mod 8, and an XCD walks its chunks in
@@ -720,6 +722,7 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *cost, const 
 // kernels then carry similar work, while a run (a compact patch of the Morton order, as many
 // wavefronts as an XCD chunk) keeps its cache locality. Bitonic sort of (cost, position) keys.
 constexpr int LSORT = 256;
+static_assert(LSORT == XCD_CHUNK * (WAVE / 16), "a sorted run is one XCD chunk of 16-lane light items");
 
 __global__ __launch_bounds__(LSORT) void light_sort_kernel(uint32_t *light, const uint32_t *lcost,
                                                            const uint32_t *counts)
