@@ -477,7 +477,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
             g.cstart = ws_cstart + W.cell_base[k];
             g.pay = ws_pay + W.pay_off[k];
-            g.pstride = W.n_total;
+            g.pstride = W.pstride;
             g.pay_off = W.pay_off[k];
             g.ncells_bound = W.max_cells[k];
             build_grid(g, stream);
@@ -531,13 +531,13 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
         uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
         launch_split(flag, ids, W.h_total, (uint32_t)p.heavy_cost, tiles, heavy, light,
-                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, stream);
+                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, ws_pay + W.n_total, stream);
         SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
         launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
         BatchArgs a{};
         a.desc = table;
         a.pay = ws_pay;
-        a.pstride = (uint32_t)W.n_total;
+        a.pstride = (uint32_t)W.pstride;
         a.cstart = ws_cstart;
         a.heavy = heavy;
         a.light = light;
@@ -1013,7 +1013,7 @@ extern "C" int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_ph
     g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
     g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
     g.pay = reinterpret_cast<float4 *>(w + W.pay);
-    g.pstride = W.n_total;
+    g.pstride = W.pstride;
     g.pay_off = 0;
     g.ncells_bound = W.max_cells[0];
     build_grid(g, stream);

@@ -48,17 +48,6 @@ __device__ __forceinline__ int wave_max_i(int v)
 }
 
 template <int G>
-__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, int j)
-{
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-        const uint32_t u = __shfl_up(v, o, G);
-        if (j >= o) v += u;
-    }
-    return v;
-}
-
-template <int G>
 __device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
@@ -91,9 +80,9 @@ __device__ __forceinline__ uint32_t group_sum_u(uint32_t v)
 
 // 16-byte load at a wave-uniform base plus a 32-bit byte offset (global_load with an SGPR base: no
 // 64-bit address arithmetic per lane; payload planes stay below 4 GiB).
-__device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
+__device__ __forceinline__ float4 ldb(const float4 *base, uint32_t off)
 {
-    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + (idx << 4));
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
 constexpr int UNROLL = 8;         // candidate loads in flight per lane
@@ -107,8 +96,8 @@ constexpr int QCAP = DRAIN + 1;    // queue capacity per kernel, in multiples of
 template <int CH>
 struct Lds {
     float4 slot[NG * CH][WAVE];   // lane-private pairs (S, err S, Q, err Q) per channel and group
-    uint32_t dl[WAVE];            // row start in the payload minus the row's offset in the concatenation
-    uint32_t re[WAVE];            // row end in the concatenation (inclusive scan)
+    uint32_t dl[WAVE];            // row start, byte offset into the position plane
+    uint32_t re[WAVE];            // row end (exclusive), byte offset into the position plane
     uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: a ring of 3 G per kernel
 };
 
@@ -140,14 +129,16 @@ struct Cand {
     float4 a, b, f;
 };
 
+// A queued photon is held as the byte offset of its plane-A entry; its (B, C) pair lies at twice that
+// offset from the pair plane's base.
 template <bool NRM, bool VCM>
-__device__ __forceinline__ Cand load_cand(uint32_t pi, const float4 *rA, const float4 *rBC)
+__device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rA, const float4 *rBC)
 {
     Cand P;
-    P.a = ld4(rA, pi);
-    P.f = ld4(rBC, 2u * pi + 1u);
+    P.a = ldb(rA, off);
+    P.f = ldb(rBC, 2u * off + 16u);
     P.b = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-    if (NRM || VCM) P.b = ld4(rBC, 2u * pi);
+    if (NRM || VCM) P.b = ldb(rBC, 2u * off);
     return P;
 }
 
@@ -214,14 +205,16 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
 }
 
 // Each kernel's queue is a ring of QCAP G entries starting at `head` (mod QCAP G; head mod G also
-// counts the kernel's photons accumulated so far, mod G). A drain takes from every kernel the
-// largest multiple of G up to DRAIN G that it holds (everything up to DRAIN G when `flush`): lane j
-// takes the photons whose positions in the kernel's in-disk stream are congruent to j mod G, in
-// stream order, so every lane sums a fixed subsequence of the stream whatever the drain times
-// (which depend on the other kernels of the wave), and the result of a kernel does not depend on
-// its neighbours in the launch. The loads of a lane's photons are issued together, then the
-// photons are added in order. Drains are called when some kernel holds DRAIN G photons; afterwards
-// every kernel holds fewer than G, so a step's push (at most G) never overwrites a queued photon.
+// counts the kernel's photons accumulated so far, mod G). A drain takes from every kernel whatever
+// it holds, up to DRAIN G photons: lane j takes the photons whose positions in the kernel's in-disk
+// stream are congruent to j mod G, in stream order, so every lane sums a fixed subsequence of the
+// stream whatever the drain times and sizes (which depend on the other kernels of the wave), and the
+// result of a kernel does not depend on its neighbours in the launch. Taking the partial queues of
+// the other kernels too keeps them from triggering drains of their own soon after, so fewer drains
+// run with idle lanes. The loads of a lane's photons are issued together, then the photons are
+// added in order. Drains are called when some kernel holds DRAIN G photons (less than QCAP G);
+// afterwards every kernel holds fewer than G, so a step's push (at most G) never overwrites a
+// queued photon.
 template <int G>
 __device__ __forceinline__ uint32_t ring(uint32_t i)
 {
@@ -229,13 +222,12 @@ __device__ __forceinline__ uint32_t ring(uint32_t i)
 }
 
 template <int G, bool NRM, bool VCM, int CH>
-__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, bool flush, int j, int base,
+__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j, int base,
                                            const Query &K, float cos_min, const float4 *rA, const float4 *rBC,
                                            Lds<CH> &L, int lane, Acc &c)
 {
     __syncthreads();
-    const uint32_t cap = (qlen < (uint32_t)(DRAIN * G)) ? qlen : (uint32_t)(DRAIN * G);
-    const uint32_t n = flush ? cap : (cap & ~(uint32_t)(G - 1));
+    const uint32_t n = (qlen < (uint32_t)(DRAIN * G)) ? qlen : (uint32_t)(DRAIN * G);
     const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
     Cand P[DRAIN];
 #pragma unroll
@@ -320,6 +312,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const float wy = 1.0f / hdr->cell_inv[1], wz = 1.0f / hdr->cell_inv[2];
     const int nbatch = wave_max_i((nrows + G - 1) / G);
 
+    const uint32_t sent = (A.pstride - 1u) << 4;   // byte offset of the point at infinity
     for (int b = 0; b < nbatch; ++b) {
         const int row = b * G + j;
         uint32_t st = 0, len = 0;
@@ -332,38 +325,42 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             len = cstart[cell + (uint32_t)x1 + 1u] - s0;
             st = s0 + D.pay_off;
         }
-        const uint32_t inc = group_incl_scan<G>(len, j);
-        const uint32_t total = __shfl(inc, base + G - 1, WAVE);
+        const uint32_t total = group_sum_u<G>(len);
         __syncthreads();
-        L.dl[lane] = st - (inc - len);
-        L.re[lane] = inc;
+        L.dl[lane] = st << 4;                     // row start and end, byte offsets into plane A
+        L.re[lane] = (st + len) << 4;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
         ncand += total;
-        // Per-lane cursor over the concatenated rows: photon index = virtual index + delta of its row.
-        // Loads are issued U steps at a time (U independent 16-byte loads in flight per lane), then
+        // Per-lane cursor over the concatenated rows, as a byte offset into plane A: lane j takes the
+        // photons at positions j, j + G, ... of the concatenation. Passing a row's end carries the
+        // overshoot into the next row; past the last non-empty row the cursor rests on the point at
+        // infinity. Loads are issued U steps at a time (U independent loads in flight per lane), then
         // the U candidates are tested from registers; those inside the disk are queued.
+        const uint64_t nonempty = __ballot(len > 0u) & gmask;
+        const int last = nonempty ? (63 - __clzll((long long)nonempty)) - base : -1;
         int cur = 0;
-        uint32_t row_end = L.re[base];
-        uint32_t delta = L.dl[base];
-        uint32_t vi = (uint32_t)j;
+        uint32_t end = L.re[base];
+        uint32_t off = L.dl[base] + ((uint32_t)j << 4);
+        uint32_t stride = (uint32_t)G << 4;
         for (int s0 = 0; s0 < nsteps; s0 += UNROLL) {
             float4 a[UNROLL];
-            uint32_t pis[UNROLL];
+            uint32_t offs[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                pis[u] = 0u;
-                a[u] = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);   // no candidate: never inside
-                if (vi < total) {
-                    while (vi >= row_end) {
-                        ++cur;
-                        row_end = L.re[base + cur];
-                        delta = L.dl[base + cur];
+                while (off >= end) {
+                    if (++cur > last) {
+                        off = sent;
+                        stride = 0u;
+                        end = 0xFFFFFFFFu;
+                    } else {
+                        off = (off - end) + L.dl[base + cur];
+                        end = L.re[base + cur];
                     }
-                    pis[u] = vi + delta;
-                    a[u] = ld4(rA, pis[u]);
                 }
-                vi += G;
+                offs[u] = off;
+                a[u] = ldb(rA, off);
+                off += stride;
             }
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
@@ -375,10 +372,10 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                 const uint64_t mk = __ballot(in) & gmask;
                 const uint32_t before =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = pis[u];
+                if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = offs[u];
                 qlen += (uint32_t)__popcll(mk);
                 if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
-                    drain_once<G, NRM, VCM, CH>(qlen, head, false, j, base, K, A.cos_min, rA, rBC, L, lane, c);
+                    drain_once<G, NRM, VCM, CH>(qlen, head, j, base, K, A.cos_min, rA, rBC, L, lane, c);
             }
         }
     }
@@ -409,7 +406,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     for (int cc = 0; cc < 6; ++cc) tv[cc] = lead ? fslot(SL_TAU + cc)[q] : 0.0f;
 
     while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM, CH>(qlen, head, true, j, base, K, A.cos_min, rA, rBC, L, lane, c);
+        drain_once<G, NRM, VCM, CH>(qlen, head, j, base, K, A.cos_min, rA, rBC, L, lane, c);
     __syncthreads();
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
@@ -678,10 +675,14 @@ void launch_cost(const ListLaunch &l, hipStream_t s)
 // the ranks inside it.
 __global__ __launch_bounds__(256) void split_kernel(const uint32_t *cost, const uint32_t *ids, int64_t n,
                                                     uint32_t heavy_cost, const uint32_t *tile_heavy, uint32_t *heavy,
-                                                    uint32_t *light, uint32_t *lcost, uint32_t *counts)
+                                                    uint32_t *light, uint32_t *lcost, uint32_t *counts,
+                                                    float4 *sentinel)
 {
     constexpr int PER = SPLIT_TILE / 256;
     __shared__ uint32_t off_s;
+    // the payload's last position entry: a point at infinity, the gather's stand-in once a lane has
+    // walked past its kernel's last row (outside every disk, never queued)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sentinel = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     if (threadIdx.x == 0) {
         uint32_t o = 0;
         for (uint32_t t = 0; t < blockIdx.x; ++t) o += tile_heavy[t];
@@ -753,11 +754,12 @@ __global__ __launch_bounds__(LSORT) void light_sort_kernel(uint32_t *light, cons
 }
 
 void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost, const uint32_t *tile_heavy,
-                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, hipStream_t s)
+                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, float4 *sentinel,
+                  hipStream_t s)
 {
     if (n <= 0) return;
     split_kernel<<<(int)cdiv(n, SPLIT_TILE), 256, 0, s>>>(cost, ids, n, heavy_cost, tile_heavy, heavy, light, lcost,
-                                                          counts);
+                                                          counts, sentinel);
     light_sort_kernel<<<(int)cdiv(n, LSORT), LSORT, 0, s>>>(light, lcost, counts);
 }
 

@@ -174,6 +174,7 @@ inline uint32_t max_cells_for(int64_t n_photons)
 struct WsLayout {
     int n_sets = 0;
     int64_t n_total = 0, h_total = 0, n_max = 0;
+    int64_t pstride = 0;      // payload plane entries: the batch's photons, then one point at infinity
     size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
     size_t cstart = 0, pay = 0;
     size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, lcost = 0, counts = 0, desc = 0;
@@ -215,7 +216,8 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     W.part = take(4 * (size_t)(nscan > 256 ? nscan : 256));   // scan partials, or the 256 digit totals
     W.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
     W.cstart = take(4 * (size_t)(cells + 1));
-    W.pay = take(16 * (size_t)W.n_total * PAY_VEC + 256);     // plane stride: n_total photons
+    W.pstride = W.n_total + 1;
+    W.pay = take(16 * (size_t)W.pstride * PAY_VEC + 256);
     const size_t hk = 4 * (size_t)(W.h_total + 1);
     W.flag = take(hk);
     W.ids = take(hk);

@@ -62,7 +62,7 @@ struct ListLaunch {
 struct BatchArgs {
     const SetDesc *desc;     // per-set table (device)
     const float4 *pay;       // combined payload: plane v at pay + v * pstride
-    uint32_t pstride;
+    uint32_t pstride;        // the batch's photons, then (plane A only) one point at infinity
     const uint32_t *cstart;  // combined cell starts (set-local positions)
     const uint32_t *heavy, *light, *counts;   // work list, entries (set << Q_BITS) | kernel
     float k;
@@ -146,7 +146,8 @@ void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, in
                   hipStream_t s);
 void launch_cost(const ListLaunch &l, hipStream_t s);
 void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost, const uint32_t *tile_heavy,
-                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, hipStream_t s);
+                  uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, float4 *sentinel,
+                  hipStream_t s);
 void launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   // bytes: multiple of 4
 void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
