@@ -77,7 +77,7 @@ typedef struct hk_params {
     int32_t stats_channel; /* HK_STATS_LUMA or HK_STATS_RGB */
     float normal_cos_min;  /* a pair counts only if n_kernel . n_photon >= this (when both have normals) */
     int32_t max_iters;     /* iterations a set may run (sizes the critical-value table), 1..65536 */
-    float cell_scale;      /* grid cell = cell_scale * (radius quantile); 0 selects the default */
+    float cell_scale;      /* grid cell (y, z) = cell_scale * (radius quantile), x a quarter of it; 0: default */
     float cell_quantile;   /* radius quantile in (0, 1] used for the cell size; 0 selects the default */
     int32_t heavy_cost;    /* kernels whose grid stencil holds more photons are heavy; 0: default */
     int32_t lanes_light;   /* lanes of a wavefront per light kernel: 4, 8 or 16; 0: default */

@@ -98,7 +98,7 @@ struct Lds {
     float4 slot[NG * CH][WAVE];   // lane-private pairs (S, err S, Q, err Q) per channel and group
     uint32_t dl[WAVE];            // row start, byte offset into the position plane
     uint32_t re[WAVE];            // row end (exclusive), byte offset into the position plane
-    uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: a ring of 3 G per kernel
+    uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: 3 G per kernel
 };
 
 // Per-kernel constants of one work item, held in registers by the kernel's G lanes.
@@ -204,23 +204,17 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
     c.cnt += ok ? 1u : 0u;
 }
 
-// Each kernel's queue is a ring of QCAP G entries starting at `head` (mod QCAP G; head mod G also
-// counts the kernel's photons accumulated so far, mod G). A drain takes from every kernel whatever
-// it holds, up to DRAIN G photons: lane j takes the photons whose positions in the kernel's in-disk
-// stream are congruent to j mod G, in stream order, so every lane sums a fixed subsequence of the
-// stream whatever the drain times and sizes (which depend on the other kernels of the wave), and the
-// result of a kernel does not depend on its neighbours in the launch. Taking the partial queues of
-// the other kernels too keeps them from triggering drains of their own soon after, so fewer drains
-// run with idle lanes. The loads of a lane's photons are issued together, then the photons are
-// added in order. Drains are called when some kernel holds DRAIN G photons (less than QCAP G);
-// afterwards every kernel holds fewer than G, so a step's push (at most G) never overwrites a
-// queued photon.
-template <int G>
-__device__ __forceinline__ uint32_t ring(uint32_t i)
-{
-    return (i >= (uint32_t)(QCAP * G)) ? i - (uint32_t)(QCAP * G) : i;     // i < 2 QCAP G
-}
-
+// Each kernel's queue holds up to QCAP G entries from its start; `head` counts the kernel's photons
+// accumulated so far, mod G. A drain takes from every kernel whatever it holds, up to DRAIN G
+// photons: lane j takes the photons whose positions in the kernel's in-disk stream are congruent to
+// j mod G, in stream order, so every lane sums a fixed subsequence of the stream whatever the drain
+// times and sizes (which depend on the other kernels of the wave), and the result of a kernel does
+// not depend on its neighbours in the launch. Taking the partial queues of the other kernels too
+// keeps them from triggering drains of their own soon after, so fewer drains run with idle lanes.
+// The loads of a lane's photons are issued together, then the photons are added in order. Drains
+// are called when some kernel holds DRAIN G photons (less than QCAP G); afterwards every kernel holds
+// fewer than G, moved to the front of its queue, so a step's push (at most G) appends without
+// wrapping and never overwrites a queued photon.
 template <int G, bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j, int base,
                                            const Query &K, float cos_min, const float4 *rA, const float4 *rBC,
@@ -233,12 +227,18 @@ __device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j
 #pragma unroll
     for (int i = 0; i < DRAIN; ++i)
         if (k + (uint32_t)(i * G) < n)
-            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + ring<G>(head + k + (uint32_t)(i * G))], rA, rBC);
+            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + k + (uint32_t)(i * G)], rA, rBC);
+    // the remainder (fewer than G, only when DRAIN G were taken) moves to the front: its entries
+    // lie at or beyond DRAIN G, its new places below G, and every read above precedes the writes
+    const uint32_t rest = qlen - n;
+    uint32_t mv = 0u;
+    if ((uint32_t)j < rest) mv = L.queue[QCAP * base + n + (uint32_t)j];
+    if ((uint32_t)j < rest) L.queue[QCAP * base + (uint32_t)j] = mv;
 #pragma unroll
     for (int i = 0; i < DRAIN; ++i)
         if (k + (uint32_t)(i * G) < n) accumulate<NRM, VCM, CH>(P[i], K, cos_min, L, lane, c);
-    qlen -= n;
-    head = ring<G>(head + n);
+    qlen = rest;
+    head = (head + n) & (uint32_t)(G - 1);
 }
 
 template <int G, bool NRM, bool VCM, int CH>
@@ -372,7 +372,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                 const uint64_t mk = __ballot(in) & gmask;
                 const uint32_t before =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                if (in) L.queue[QCAP * base + ring<G>(head + qlen + before)] = offs[u];
+                if (in) L.queue[QCAP * base + qlen + before] = offs[u];
                 qlen += (uint32_t)__popcll(mk);
                 if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
                     drain_once<G, NRM, VCM, CH>(qlen, head, j, base, K, A.cos_min, rA, rBC, L, lane, c);
