@@ -815,6 +815,7 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
             return fail(HK_E_INVALID_ARG, "scratch of set %d must be a separate 256-byte aligned buffer", set_ids[s]);
     HIP_TRY(hipSetDevice(ctx->device));
     static const float cells[] = {0.7f, 1.0f, 1.4f};
+    constexpr int TUNE_REPS = 3;
     constexpr int n_trials = 3 * 3 * 4;
     static const int lanes[] = {4, 8, 16};
     static const int heavies[] = {1024, 2048, 4096, 16384};
@@ -841,17 +842,24 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
             q.heavy_cost = heavies[trial % 4];
         }
         ctx->p = q;
-        rc = copy_states();
-        if (rc) break;
-        hipError_t e = hipEventRecord(e0, stream);
-        if (e == hipSuccess) {
-            rc = enqueue(ctx, n_sets, set_ids, ph, scratch, workspace, workspace_bytes, stream, false, nullptr, nullptr);
-            e = hipEventRecord(e1, stream);
+        // the fastest of TUNE_REPS runs from the same copied state (one run is at the mercy of
+        // clock ramps and other work on the device)
+        float ms = INFINITY;
+        for (int rep = 0; rep < TUNE_REPS && rc == HK_OK; ++rep) {
+            rc = copy_states();
+            if (rc) break;
+            hipError_t e = hipEventRecord(e0, stream);
+            if (e == hipSuccess) {
+                rc = enqueue(ctx, n_sets, set_ids, ph, scratch, workspace, workspace_bytes, stream, false, nullptr,
+                             nullptr);
+                e = hipEventRecord(e1, stream);
+            }
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) rc = fail(HK_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+            ms = fminf(ms, t);
         }
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) rc = fail(HK_E_HIP, "autotune timing: %s", hipGetErrorString(e));
         if (rc == HK_OK && trial >= 0 && ms < best_ms) {
             best_ms = ms;
             best = q;
