@@ -40,27 +40,26 @@ __global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t *d, int
         if (threadIdx.x == 0) part[blockIdx.x] = 0u;
         return;
     }
+    // each thread sums its own run of SCAN_TILE / 256 counters (16-byte words when they are all
+    // live and the array is 16-byte aligned)
+    constexpr int PER = SCAN_TILE / 256;
+    const int64_t first = base + (int64_t)threadIdx.x * PER;
     uint32_t s = 0;
-    for (int i = threadIdx.x; i < SCAN_TILE; i += 256) {
-        const int64_t k = base + i;
-        if (k < len) s += d[k];
+    if (first + PER <= len && (reinterpret_cast<uintptr_t>(d) & 15u) == 0) {
+#pragma unroll
+        for (int i = 0; i < PER; i += 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(d + first + i);
+            s += (x.x + x.y) + (x.z + x.w);
+        }
+    } else {
+        for (int i = 0; i < PER; ++i) {
+            const int64_t k = first + i;
+            if (k < len) s += d[k];
+        }
     }
     uint32_t tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(256) void scan_parts_kernel(uint32_t *part, int nparts)
-{
-    uint32_t carry = 0;
-    for (int base = 0; base < nparts; base += 256) {
-        const int k = base + threadIdx.x;
-        const uint32_t v = k < nparts ? part[k] : 0;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
-        if (k < nparts) part[k] = carry + ex;
-        carry += tot;
-    }
 }
 
 __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len, const uint32_t *part,
@@ -70,21 +69,58 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t *d, int64_t len
     len = live_len(len, dlen, extra);
     if ((int64_t)blockIdx.x * SCAN_TILE >= len) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
+    // a thread's PER counters as 16-byte words when they are all live and the array is 16-byte
+    // aligned (a set's cell starts begin at any 4-byte offset of the batch's array)
+    const bool vec = base + PER <= len && (reinterpret_cast<uintptr_t>(d) & 15u) == 0;
     uint32_t v[PER];
     uint32_t s = 0;
+    if (vec) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int64_t k = base + i;
-        v[i] = k < len ? d[k] : 0;
-        s += v[i];
+        for (int i = 0; i < PER; i += 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(d + base + i);
+            v[i] = x.x;
+            v[i + 1] = x.y;
+            v[i + 2] = x.z;
+            v[i + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t k = base + i;
+            v[i] = k < len ? d[k] : 0;
+        }
     }
-    uint32_t tot;
-    uint32_t run = block_excl_scan(s, &tot) + part[blockIdx.x];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int64_t k = base + i;
-        if (k < len) d[k] = run;
-        run += v[i];
+    for (int i = 0; i < PER; ++i) s += v[i];
+    // the block's offset: the partial sums of the blocks before it (each block adds them itself,
+    // which saves a one-block launch between the two sweeps)
+    uint32_t pre = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += 256) pre += part[i];
+    uint32_t off;
+    block_excl_scan(pre, &off);
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, &tot) + off;
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < PER; i += 4) {
+            uint4 x;
+            x.x = run;
+            run += v[i];
+            x.y = run;
+            run += v[i + 1];
+            x.z = run;
+            run += v[i + 2];
+            x.w = run;
+            run += v[i + 3];
+            *reinterpret_cast<uint4 *>(d + base + i) = x;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t k = base + i;
+            if (k < len) d[k] = run;
+            run += v[i];
+        }
     }
 }
 
@@ -92,7 +128,6 @@ void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const ui
 {
     const int nparts = (int)cdiv(len, SCAN_TILE);
     scan_reduce_kernel<<<nparts, 256, 0, s>>>(d, len, part, dlen, extra);
-    scan_parts_kernel<<<1, 256, 0, s>>>(part, nparts);
     scan_down_kernel<<<nparts, 256, 0, s>>>(d, len, part, dlen, extra);
 }
 
