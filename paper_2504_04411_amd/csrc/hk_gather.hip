@@ -679,41 +679,59 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *cost, const 
                                                     float4 *sentinel)
 {
     constexpr int PER = SPLIT_TILE / 256;
-    __shared__ uint32_t off_s;
     // the payload's last position entry: a point at infinity, the gather's stand-in once a lane has
     // walked past its kernel's last row (outside every disk, never queued)
     if (blockIdx.x == 0 && threadIdx.x == 0) *sentinel = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    if (threadIdx.x == 0) {
-        uint32_t o = 0;
-        for (uint32_t t = 0; t < blockIdx.x; ++t) o += tile_heavy[t];
-        off_s = o;
-    }
+    // heavy entries of the tiles before this one, summed by the whole block
+    uint32_t hb = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += 256) hb += tile_heavy[t];
+    uint32_t before;
+    block_excl_scan(hb, &before);
     const int64_t base = (int64_t)blockIdx.x * SPLIT_TILE + (int64_t)threadIdx.x * PER;
+    // a thread's PER entries as 16-byte words when they are all present and both arrays are 16-byte
+    // aligned (a set's entries begin at any 4-byte offset of the batch's arrays)
+    const bool vec = base + PER <= n && ((reinterpret_cast<uintptr_t>(cost) | reinterpret_cast<uintptr_t>(ids)) & 15u) == 0;
+    uint32_t cv[PER], iv[PER];
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < PER; i += 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(cost + base + i);
+            const uint4 y = *reinterpret_cast<const uint4 *>(ids + base + i);
+            cv[i] = x.x, cv[i + 1] = x.y, cv[i + 2] = x.z, cv[i + 3] = x.w;
+            iv[i] = y.x, iv[i + 1] = y.y, iv[i + 2] = y.z, iv[i + 3] = y.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            cv[i] = base + i < n ? cost[base + i] : 0u;
+            iv[i] = base + i < n ? ids[base + i] : 0u;
+        }
+    }
     uint32_t f[PER];
     uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        f[i] = (base + i < n && cost[base + i] > heavy_cost) ? 1u : 0u;
+        f[i] = (base + i < n && cv[i] > heavy_cost) ? 1u : 0u;
         c += f[i];
     }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(c, &tot);         // synchronises the block (off_s is set)
-    uint32_t o = off_s + ex;
+    const uint32_t ex = block_excl_scan(c, &tot);
+    uint32_t o = before + ex;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int64_t q = base + i;
         if (q < n) {
             if (f[i]) {
-                heavy[o] = ids[q];
+                heavy[o] = iv[i];
             } else {
-                light[(uint32_t)q - o] = ids[q];
-                lcost[(uint32_t)q - o] = cost[q];
+                light[(uint32_t)q - o] = iv[i];
+                lcost[(uint32_t)q - o] = cv[i];
             }
         }
         o += f[i];
     }
     if ((int64_t)(blockIdx.x + 1) * SPLIT_TILE >= n && threadIdx.x == 0) {
-        const uint32_t nh = off_s + tot;
+        const uint32_t nh = before + tot;
         counts[0] = nh;
         counts[1] = (uint32_t)n - nh;
     }

@@ -384,10 +384,19 @@ __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, 
     bc[1] = make_float4(R, G, B, dvcm);
 }
 
+// Four counters per thread: one 16-byte store when all four are live and the array is 16-byte
+// aligned, else one store each.
+constexpr int ZERO_PER = 4;
 __global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t n, const uint32_t *dlen, int extra)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < live_len(n, dlen, extra)) p[i] = 0u;
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * ZERO_PER;
+    const int64_t len = live_len(n, dlen, extra);
+    if (i + ZERO_PER <= len && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        *reinterpret_cast<uint4 *>(p + i) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int k = 0; k < ZERO_PER; ++k)
+            if (i + k < len) p[i + k] = 0u;
+    }
 }
 
 // Photons per cell from the sorted keys: the first lane of every run of equal keys inside a
@@ -410,7 +419,7 @@ __global__ __launch_bounds__(256) void cell_count_kernel(const SetHeader *hdr, c
 
 void launch_zero(uint32_t *p, int64_t n, hipStream_t s)
 {
-    if (n > 0) zero_kernel<<<(int)cdiv(n, 256), 256, 0, s>>>(p, n, nullptr, 0);
+    if (n > 0) zero_kernel<<<(int)cdiv(n, 256 * ZERO_PER), 256, 0, s>>>(p, n, nullptr, 0);
 }
 
 void build_grid(const GridLaunch &g, hipStream_t s)
@@ -419,7 +428,7 @@ void build_grid(const GridLaunch &g, hipStream_t s)
     // counts of every cell of this iteration's plan, then their scan: the arrays are sized for the
     // workspace bound, the plan's cell count (on the device) limits the work
     const int64_t nc = (int64_t)g.ncells_bound + 1;
-    zero_kernel<<<(int)cdiv(nc, 256), 256, 0, s>>>(g.cstart, nc, &g.hdr->ncells, 1);
+    zero_kernel<<<(int)cdiv(nc, 256 * ZERO_PER), 256, 0, s>>>(g.cstart, nc, &g.hdr->ncells, 1);
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
         keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
