@@ -257,25 +257,33 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
 // cell 0.7 r) without adding rows; the cost is CELL_XSUB times more cell starts to zero and scan.
 constexpr float CELL_XSUB = 4.0f;
 
-// One thread: advance the set's iteration counter, append J to the prefix sums, choose the cell size
-// from the radius histogram (y and z; x a CELL_XSUB-th of it). Everything that changes between
-// iterations lives in the state, so a captured graph can replay the iteration.
+// One wavefront: advance the set's iteration counter, append J to the prefix sums, choose the cell
+// size from the radius histogram (y and z; x a CELL_XSUB-th of it). The quantile's bin is the
+// largest b whose count of radii in bins >= b reaches the target: lane b holds bin b, the counts
+// from the top come from a suffix scan. Everything that changes between iterations lives in the
+// state, so a captured graph can replay the iteration.
+static_assert(RHIST_BINS == WAVE, "one lane per radius bin");
 __global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile,
                             uint32_t max_cells)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    const int b = (int)threadIdx.x;
+    uint64_t above = hdr->rhist[b];
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const uint64_t v = __shfl_down(above, o, WAVE);
+        if (b + o < WAVE) above += v;
+    }
+    const double target = (double)quantile * hdr->H;
+    const uint64_t reach = __ballot((double)above >= target);
+    const int bq = reach ? 63 - __clzll((long long)reach) : 0;
+    hdr->rhist[b] = 0;
+    if (b != 0) return;
     const int iter = hdr->iter + 1;
     hdr->iter = iter;
     hdr->Jf = (float)J;
     hdr->n_launch += 1ull;
     mprefix[iter] = mprefix[iter - 1] + J;
-    const double target = (double)quantile * hdr->H;
-    double cum = 0.0;
-    int bq = 0;
-    for (int b = RHIST_BINS - 1; b >= 0; --b) {
-        cum += hdr->rhist[b];
-        if (cum >= target) { bq = b; break; }
-    }
     float cell = cell_scale * hdr->r1 * exp2f(-0.25f * (float)bq);
     float ext[3];
     int flat[3];
@@ -304,7 +312,6 @@ __global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cel
     }
     hdr->ncells = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2];
     hdr->cell = cell;
-    for (int b = 0; b < RHIST_BINS; ++b) hdr->rhist[b] = 0;
 }
 
 // One thread: a grid of fixed cell size `cell` (grown until the cell count fits max_cells) over the
