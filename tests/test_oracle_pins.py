@@ -436,3 +436,72 @@ def test_vcm_weight_limits(oracle_mod):
     np.testing.assert_allclose(small, small[0], rtol=1e-3)
     eta = 1000 * math.pi * rs[0] ** 2
     np.testing.assert_allclose(ws[0], eta / (eta + 0.7 + 0.4), rtol=1e-4)
+
+
+def _one_pair_weight(oracle_mod, r, J, cam, light):
+    """Merge weight w of a single light vertex lying on a single camera vertex, read back from the
+    gathered flux (throughputs of one, so the flux sum is w itself). cam and light are the partials
+    (dVCM, dVC, dVM)."""
+    ks = G.KernelSet(pos=np.array([[0.5], [0.5], [0.0]], F32), nrm=np.array([[0.0], [0.0], [1.0]], F32),
+                     cam_beta=np.ones((3, 1), F32), cam_mis=np.array(cam, F32).reshape(3, 1))
+    ph = G.PhotonBatch(J=J, pos=np.array([[0.5], [0.5], [0.0]], F32), flux=np.ones((3, 1), F32),
+                       nrm=np.array([[0.0], [0.0], [1.0]], F32), mis=np.array(light, F32).reshape(3, 1))
+    g = oracle_mod.gather(ks, ph, np.array([r], F32), vcm=True)
+    assert g.count[0] == 1
+    return g.flux[0, 0]
+
+
+def test_vcm_weight_merging_partial_term(oracle_mod):
+    """Eq. mis-weight with the vertex-connection partials dVCM zero on both sides: only the dVM p
+    terms remain, and with a direction pdf of 1/pi (Lambertian at normal incidence) the weight is
+    1 / (1 + (dVM_L + dVM_C) / pi) whatever the radius (no eta left in it). Dropping the dVM term
+    would give 1; a pdf of 1 would give 1 / (1 + dVM_L + dVM_C)."""
+    for dvm_l, dvm_c in ((0.3, 0.2), (1.0, 0.0), (0.0, 2.5), (0.9, 0.6)):
+        want = 1.0 / (1.0 + (dvm_l + dvm_c) / math.pi)
+        for r in (1e-4, 3e-3, 0.05, 2.0):
+            for J in (1, 1000, 4_000_000):
+                got = _one_pair_weight(oracle_mod, r, J, (0.0, 0.9, dvm_c), (0.0, 0.8, dvm_l))
+                assert abs(got - want) <= 4e-7 * want, (dvm_l, dvm_c, r, J, got, want)
+
+
+def test_vcm_weight_mixed_hand_evaluated(oracle_mod):
+    """All four partials non-zero, evaluated by hand: J = 1000, r = 0.01 give eta = J pi r^2 = pi/10;
+    W_L = 0.4 / eta + 0.3 / pi = 4.3 / pi and W_C = 0.7 / eta + 0.2 / pi = 7.2 / pi, so
+    w = 1 / (1 + 11.5 / pi) = pi / (pi + 11.5) ~ 0.2145663. dVC (0.55, 0.45 here) plays no part in
+    merging."""
+    got = _one_pair_weight(oracle_mod, 0.01, 1000, (0.7, 0.55, 0.2), (0.4, 0.45, 0.3))
+    want = math.pi / (math.pi + 11.5)
+    assert abs(want - 0.2145663) < 1e-7
+    assert abs(got - want) <= 4e-7 * want, (got, want)
+
+
+# ---------------------------------------------------------------------------------------------
+# no test while the within-group degrees of freedom vanish (Sec. 3.2.2: d2 = n (m - 1))
+# ---------------------------------------------------------------------------------------------
+
+def test_single_emitted_subpath_has_no_test(oracle_mod):
+    """J_emitted = 1 gives m = 1 sample per group, so F(n - 1, n (m - 1)) has no within-group degrees
+    of freedom: no critical value (NaN), no F, the radius is kept. The estimate still takes the
+    light vertex: tau = flux / (J pi r^2). One more iteration with J = 1 gives m = 2 and the test
+    resumes against the quantile of F(11, 12) (d2 = 12, not 24 or 11)."""
+    ks = G.KernelSet(pos=np.array([[0.5], [0.5], [0.0]], F32))
+    p = G.Params(r1=0.05)
+    st = oracle_mod.init_state(1, p.r1)
+    ph1 = G.PhotonBatch(J=1, pos=np.array([[0.51], [0.5], [0.0]], F32), flux=np.array([[2.0], [1.0], [0.5]], F32))
+    oracle_mod.iterate(p, ks, st, ph1)
+    assert st.count[0] == 1 and st.m[0] == 1.0
+    assert np.isnan(st.Fc[0]) and np.isnan(st.F[0]) and not st.shrink[0]
+    assert st.r[0] == F32(0.05) and st.t[0] == 1
+    np.testing.assert_allclose(st.tau[0], np.array([2.0, 1.0, 0.5]) / (math.pi * float(F32(0.05)) ** 2), rtol=1e-12)
+    # second sub-path in another sector: m = 2, d2 = 12
+    ph2 = G.PhotonBatch(J=1, pos=np.array([[0.49], [0.5], [0.0]], F32), flux=np.array([[2.0], [1.0], [0.5]], F32))
+    oracle_mod.iterate(p, ks, st, ph2)
+    assert st.m[0] == 2.0
+    np.testing.assert_allclose(st.Fc[0], stats.f.ppf(0.95, 11, 12), rtol=1e-9)
+    # two equal samples in two of the 12 groups (sectors 3 and 0 of the inner annulus), zero padding
+    # elsewhere: one-way ANOVA of the explicit 12 x 2 matrix (F is scale-invariant and does not
+    # depend on which two groups)
+    groups = [np.zeros(2) for _ in range(12)]
+    groups[0][0] = 1.0
+    groups[1][1] = 1.0
+    np.testing.assert_allclose(st.F[0], stats.f_oneway(*groups).statistic, rtol=1e-6)
