@@ -133,7 +133,12 @@ int hk_workspace_bytes(hk_ctx *ctx, int64_t max_photons, int64_t max_kernels, si
  * ratio rmin / r1), so sets of different scales can share a context and a batch. Inputs (device):
  * pos[3]; nrm[3] or NULL (+z); r_init or NULL; VCM only: cam_beta[3] camera throughput, cam_mis[3]
  * partials dVCM, dVC, dVM. `workspace` (device, at least hk_workspace_bytes(ctx, 0, n) bytes, given
- * in workspace_bytes) is scratch for the ordering. Resets the set's iteration count. */
+ * in workspace_bytes) is scratch for the ordering. Resets the set's iteration count.
+ * r_init (device, n radii in the caller's order) must hold finite radii >= the first lower bound
+ * r_min (float32): the lower bounds decrease, so every radius then stays at or above the bound and a
+ * shrink (Eq. radiusupdate) never makes it grow. With r_init given the call checks it on the device
+ * and synchronises `stream`; HK_E_INVALID_ARG (the set stays uninitialised) names how many radii
+ * failed. Without r_init it does not synchronise. */
 int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, const float *const pos[3],
                    const float *const nrm[3], const float *r_init, const float *const cam_beta[3],
                    const float *const cam_mis[3], void *state, void *workspace, size_t workspace_bytes,

@@ -82,6 +82,8 @@ struct hk_graph {
 
 static bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
 
+static int ensure_streams(hk_ctx *ctx);
+
 extern "C" int hk_version(void) { return HK_VERSION; }
 
 extern "C" const char *hk_last_error(void) { return g_err.c_str(); }
@@ -156,6 +158,12 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(HK_E_HIP, "hipGetDevice failed");
+    }
+    // set-up that later calls must not repeat: the second stream and its events
+    rc = ensure_streams(c);
+    if (rc) {
+        (void)hk_destroy(c);
+        return rc;
     }
     *out = c;
     return HK_OK;
@@ -277,15 +285,26 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, dou
     g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
     g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
     g.part = reinterpret_cast<uint32_t *>(w + W.part);
-    init_set(g, stream);
-    // lower bounds lb_i = r_min sqrt(i^(alpha - 1)) of Eq. radiusupdate, float64 then one rounding
+    // lower bounds lb_i = r_min sqrt(i^(alpha - 1)) of Eq. radiusupdate, float64 then one rounding;
+    // they decrease with i, so a radius at or above lb_1 = r_min never grows on a shrink
     std::vector<float> lb((size_t)ctx->p.max_iters + 2);
     for (size_t i = 0; i < lb.size(); ++i)
         lb[i] = (float)(rmin * sqrt(pow((double)(i > 0 ? i : 1), ctx->p.alpha - 1.0)));
+    g.r_floor = lb[1];
+    SetInfo &S = ctx->sets[set_id];
+    S = SetInfo();                 // uninitialised until the set-up below has succeeded
+    init_set(g, stream);
     launch_upload(g.st.lbtab, lb.data(), sizeof(float) * lb.size(), stream);
     HIP_TRY(hipGetLastError());
-    SetInfo &S = ctx->sets[set_id];
-    S = SetInfo();
+    if (r_init) {
+        // caller radii are checked on the device; the count comes back synchronously
+        uint32_t nbad = 0;
+        HIP_TRY(hipMemcpyAsync(&nbad, &g.st.hdr->n_bad_r, sizeof nbad, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (nbad)
+            return fail(HK_E_INVALID_ARG, "r_init: %u of %lld radii are not finite or below r_min = %g", nbad,
+                        (long long)n, (double)lb[1]);
+    }
     S.init = true;
     S.gen = ++ctx->gen;
     S.H = n;

@@ -455,25 +455,35 @@ void build_grid(const GridLaunch &g, hipStream_t s)
 // One block: bounding box of the kernels, largest initial radius, grid domain and header fields.
 __global__ __launch_bounds__(1024) void bbox_kernel(SetHeader *hdr, double *mprefix, int max_iters,
                                                     const float *px, const float *py, const float *pz,
-                                                    const float *r_init, int64_t n, float r1, int has_nrm,
-                                                    int vcm)
+                                                    const float *r_init, int64_t n, float r1, float r_floor,
+                                                    int has_nrm, int vcm)
 {
     __shared__ float red[7][16];
+    __shared__ uint32_t nbad[16];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, rm = r1;
+    uint32_t bad = 0;
     for (int64_t i = threadIdx.x; i < n; i += 1024) {
         const float p[3] = {px[i], py[i], pz[i]};
         for (int a = 0; a < 3; ++a) {
             lo[a] = fminf(lo[a], p[a]);
             hi[a] = fmaxf(hi[a], p[a]);
         }
-        if (r_init) rm = fmaxf(rm, r_init[i]);
+        if (r_init) {
+            const float r = r_init[i];
+            // a radius below the first lower bound could grow at its first shrink (Eq. radiusupdate)
+            bad += (isfinite(r) && r > 0.0f && r >= r_floor) ? 0u : 1u;
+            rm = fmaxf(rm, r);
+        }
     }
     float v[7] = {lo[0], lo[1], lo[2], -hi[0], -hi[1], -hi[2], -rm};
     for (int k = 0; k < 7; ++k)
         for (int o = 32; o > 0; o >>= 1) v[k] = fminf(v[k], __shfl_xor(v[k], o, 64));
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0)
+    if (lane == 0) {
         for (int k = 0; k < 7; ++k) red[k][w] = v[k];
+        nbad[w] = bad;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 0; k < 7; ++k) {
@@ -481,6 +491,9 @@ __global__ __launch_bounds__(1024) void bbox_kernel(SetHeader *hdr, double *mpre
             for (int i = 1; i < 16; ++i) m = fminf(m, red[k][i]);
             v[k] = m;
         }
+        uint32_t nb = 0;
+        for (int i = 0; i < 16; ++i) nb += nbad[i];
+        hdr->n_bad_r = nb;
         float kl[3] = {v[0], v[1], v[2]}, kh[3] = {-v[3], -v[4], -v[5]};
         const float rmax = -v[6];
         float scale = 0.0f;
@@ -593,7 +606,7 @@ void init_set(const InitLaunch &g, hipStream_t s)
 {
     const int64_t n = g.n;
     bbox_kernel<<<1, 1024, 0, s>>>(g.st.hdr, g.st.mprefix, g.max_iters, g.src.pos[0], g.src.pos[1], g.src.pos[2],
-                                   g.src.r_init, n, g.r1, g.src.nrm[0] != nullptr, g.vcm);
+                                   g.src.r_init, n, g.r1, g.r_floor, g.src.nrm[0] != nullptr, g.vcm);
     const int nb = (int)cdiv(n, 256);
     morton_kernel<<<nb, 256, 0, s>>>(g.st.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
     uint32_t *ks, *vs;

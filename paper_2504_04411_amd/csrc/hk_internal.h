@@ -41,7 +41,8 @@ struct SetHeader {
     float cell;
     int32_t iter;            // iterations started (the plan kernel advances it)
     float Jf;                // J_emitted of the current iteration
-    int32_t pad[2];
+    uint32_t n_bad_r;        // caller radii (r_init) that are not finite or below r_min, counted at set-up
+    int32_t pad;
     // running totals since hk_set_kernels (gather launches, in-disk pairs, lane x photon tests)
     unsigned long long n_launch;
     unsigned long long n_pairs;

@@ -38,6 +38,7 @@ struct InitLaunch {
     int64_t n;
     int max_iters;
     float r1;
+    float r_floor;           // smallest admissible caller radius: the first lower bound, r_min
     int vcm;
     uint32_t *keyA, *keyB, *valA, *valB, *hist, *part;
 };

@@ -169,3 +169,46 @@ def test_compensated_sums_error_against_float64():
     bound = 16 * 100_000 * u * u
     assert eS < bound and eQ < bound and rel_tau < 1e-6
     est.close()
+
+
+def test_lower_bound_binds():
+    """Eq. radiusupdate's lower bound r_min sqrt((i+1)^(alpha-1)) reached on the device: box 40 x 40
+    with r_min = 0.3 r1 and k = 0.5, 12 iterations. Radii are compared bit for bit every iteration,
+    and many kernels must sit exactly on the bound of the iteration that shrank them."""
+    from oracle import oracle as O
+    from paper_2504_04411_amd.estimator import DevicePhotons
+    G = _G()
+    P = _parity()
+    w = G.box_scene(seed=1, res=40, J=200_000, n_iter=12)
+    w.params.k = 0.5
+    w.params.rmin = 0.3 * w.params.r1
+    est = P.make_estimator(w)
+    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)
+    tr = P.Tracker(w)
+    on_bound = 0
+    for it in range(12):
+        ph = w.photons(it)
+        est.iterate([0], [DevicePhotons.upload(ph)])
+        tr.step(est, 0, ph)
+        lb = O.lower_bound(w.params.rmin, w.params.alpha, it + 2)
+        r = est.radii(0).cpu().numpy()
+        on_bound += int((tr.ost.shrink & (r == lb)).sum())
+        assert np.all(r >= lb)
+    rep = tr.finish(est, 0)
+    est.close()
+    print(f"  shrinks onto the lower bound: {on_bound}; {rep}", flush=True)
+    assert on_bound > 100
+
+
+def test_single_emitted_subpath_no_test():
+    """J_emitted = 1: m = 1 leaves F(11, 12 (m - 1)) without within-group degrees of freedom, so no
+    kernel is tested (critical value NaN) and every radius is kept; the next iteration with J = 1
+    (m = 2) tests against F(11, 12). Mixed with ordinary batches before and after."""
+    G = _G()
+    base = G.small_config0(seed=14, n_side=10, J=3000)
+    k = base.kernels.pos
+    one = lambda j: G.PhotonBatch(J=1, pos=np.ascontiguousarray(k[:, j:j + 1] + np.float32(0.004)),  # noqa: E731
+                                  flux=np.ones((3, 1), np.float32))
+    none = G.PhotonBatch(J=1, pos=np.zeros((3, 0), np.float32), flux=np.zeros((3, 0), np.float32))
+    seq = [one(11), one(12), none, base.photons(0), one(40), base.photons(1), one(41)]
+    _parity().run_parity(base, len(seq), photons_fn=lambda it: seq[it])

@@ -404,9 +404,47 @@ def config4(seed: int = 4, nx: int = 1920, ny: int = 1080, J: int = 4_000_000, n
     ks = KernelSet(pos=pos, nrm=nrm, cam_beta=beta, cam_mis=mis)
 
     def photons(it: int) -> PhotonBatch:
-        rng = rng_for(seed, 0, it)
-        b = _planar_batch(rng, J, J, 0.5, (0.7, 0.3), 1.0, with_nrm=True, with_mis=True)
-        return b
+        return config4_photons(seed, it, J)
 
     return Workload("vcm-merge", Params(r1=r1, n_iter=n_iter, mode="vcm"), ks, photons, seed,
                     info=dict(H=H, J=J))
+
+
+def config4_photons(seed: int, it: int, J: int = 4_000_000) -> PhotonBatch:
+    """Light vertices of config 4 at iteration it: config 0's density, normal +z, throughput
+    lognormal(0, 1), partials U[0, 1]; every emitted path is stored."""
+    return _planar_batch(rng_for(seed, 0, it), J, J, 0.5, (0.7, 0.3), 1.0, with_nrm=True, with_mis=True)
+
+
+# ---------------------------------------------------------------------------------------------
+# Batches by picklable description, for generation in worker processes
+# ---------------------------------------------------------------------------------------------
+
+def batch(spec) -> PhotonBatch:
+    """The batch a tuple describes: ("box", seed, it, J, res) for config 1's box scene,
+    ("jittered", seed, it, J, res) for config 3's scenes, ("sets", seed, s, it, J, edge, caustic)
+    for set s of config 2, ("merge", seed, it, J) for config 4."""
+    kind = spec[0]
+    if kind == "box":
+        _, seed, it, J, res = spec
+        return box_scene(seed=seed, res=res, J=J).photons(it)
+    if kind == "jittered":
+        _, seed, it, J, res = spec
+        return config3(seed, res=res, J=J).photons(it)
+    if kind == "sets":
+        _, seed, s, it, J, edge, ca = spec
+        return config2_photons(seed, s, it, J, edge, ca)
+    if kind == "merge":
+        _, seed, it, J = spec
+        return config4_photons(seed, it, J)
+    raise ValueError(f"unknown batch kind {kind!r}")
+
+
+def spawn_pool(workers: int):
+    """Worker processes for ``batch``, started with the spawn method: fresh interpreters that share
+    nothing with a parent that may already hold a GPU (no fork of such a process)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    ex = ProcessPoolExecutor(max_workers=max(1, workers), mp_context=multiprocessing.get_context("spawn"))
+    list(ex.map(int, range(max(1, workers))))          # start the workers now
+    return ex
