@@ -1,15 +1,20 @@
 """Throughput of the hypothesis-tested progressive kernel estimator on one MI355X.
 
 A step is one full iteration of the hot path (grid build, gather, grouped sums, F-test, radius and
-estimate update) over one batch of light vertices. Default workload: the box scene, 512 x 512 hit
-points on five faces of the unit box with per-point normals, 2M light sub-paths per iteration from a
-point light with a spherical occluder, 64 iterations (the whole job is timed; warm-up iterations run
-on a separate state first). Inputs are generated on the host, uploaded, and resident in HBM before
-the timed region starts.
+estimate update) over one batch of light vertices per hit-point set. The headline workload is the
+largest one: 16 independent planar hit-point sets of uneven size (64^2 to 1024^2 hit points, 0.5M to
+8M light paths each per iteration; 2.57M hit points and 41.6M light paths per iteration in all), one
+batched call per iteration. Two more workloads are measured the same way and reported beside it: the
+box scene (512 x 512 hit points with normals, 2M light paths from a point light with a spherical
+occluder) and vertex merging at scale (1920 x 1080 camera vertices, 4M light vertices with MIS
+partials). Inputs are generated on the host by spawned worker processes (nothing is forked from a
+process that holds the GPU), uploaded, and resident in HBM before any timed region starts.
 
-Prints one JSON line: value = queries/s (one query = one hit point in one iteration), with the
-roofline of the dominant kernel (fused gather / test / update) and the CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+Every workload: W untimed warm-up iterations, the autotuner on the warmed state, then R repeats of
+exactly K timed iterations, each from a fresh state; the median repeat is reported. HIP events on
+the library's own stream time the phases; the dominant kernel (the fused gather / test / update)
+gets a roofline. Prints one JSON line: value = queries/s of the headline workload (one query = one
+hit point in one iteration).
 """
 from __future__ import annotations
 
@@ -17,17 +22,17 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
-from concurrent.futures import ProcessPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# Dominant-kernel work model per launch (VALU lane operations), from the hot-path measurement model:
-# 150 per kernel (load state, F in float64, update), 35 per in-disk pair (map, group, compensated
+# Dominant-kernel VALU work model per launch (lane operations), the hot-path measurement model:
+# 150 per hit point (load state, F in float64, update), 35 per in-disk pair (map, group, compensated
 # sums), 8 per candidate with 2.9 candidates per in-disk pair (uniform grid with cell = r).
 OPS_PER_QUERY = 150.0
 OPS_PER_PAIR = 35.0 + 8.0 * 2.9
@@ -35,15 +40,24 @@ OPS_PER_PAIR = 35.0 + 8.0 * 2.9
 # (packed-FP32 and FMA doubling excluded; this build disables packed FP32).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+# Algorithmic bytes the gather / test / update must move per launch: every stored light vertex's
+# payload read once (P_b bytes) and every hit point's geometry read (G_h) and statistics read and
+# written once (2 x 232 bytes: twelve compensated (S, Q) pairs, the estimate pair, radius, counts).
+STATE_RW = 2 * 232
+WORKLOADS = {
+    "sets": dict(P_b=24, G_h=12),       # planar sets: position + flux; position
+    "box": dict(P_b=36, G_h=24),        # box: position + normal + flux; position + normal
+    "merge": dict(P_b=48, G_h=48),      # merging: position + normal + throughput + partials; + camera
+}
 
 
-def profiled_traffic(kname, tuning):
+def profiled_traffic(workload, kname, tuning):
     """HBM bytes per launch of the gather kernel from the committed rocprofv3 summary (one record per
-    tuning), or None when the kernel sources changed since the counters were taken (their hash is
-    recorded there) or no record is of this instance of the kernel and this tuning."""
+    workload, kernel instance and tuning), or None when the kernel sources changed since the counters
+    were taken (their hash is recorded there) or no record matches."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "gather_update_box.md")
+    path = os.path.join(ROOT, "profiles", "gather_traffic.md")
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -53,28 +67,186 @@ def profiled_traffic(kname, tuning):
     for m in re.finditer(r'^(\{"kernel": "gather_update_kernel".*\})$', open(path).read(), flags=re.M):
         rec = json.loads(m.group(1))
         if (h.hexdigest()[:16] == rec["source_sha256_16"] and rec.get("instance") == kname
+                and rec.get("workload") == workload
                 and [round(float(x), 4) for x in rec.get("tuning", [])] == want):
             return rec["traffic_bytes_per_launch"]
     return None
 
 
-def _gen(args):
-    seed, it, J = args
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ------------------------------------------------------------------------------------------------
+# workloads: hit-point sets and the batch descriptions the worker processes turn into light vertices
+# ------------------------------------------------------------------------------------------------
+
+def describe(name, args):
+    """(workloads, batch specs per iteration, label) of a named workload."""
     from workloads import generators as G
-    w = G.config1(seed=seed, J=J)
-    b = w.photons(it)
-    return it, b
+    n = max(args.steps, args.warmup)
+    if name == "sets":
+        meta = G.config2_sets(2)
+        ws = G.config2(seed=2)
+        specs = [[("sets", 2, s, it, J, e, c) for s, (_, J, e, c) in enumerate(meta)] for it in range(n)]
+        H = sum(w.kernels.n for w in ws)
+        label = (f"16 planar hit-point sets of uneven size (config 2, seed 2): {H} hit points and "
+                 f"{sum(m[1] for m in meta)} light paths per iteration in all, one batched call per iteration")
+    elif name == "box":
+        ws = [G.config1(seed=args.seed, res=args.res, J=args.photons)]
+        specs = [[("box", args.seed, it, args.photons, args.res)] for it in range(n)]
+        label = (f"box scene (config 1): {args.res}x{args.res} hit points with normals, {args.photons} light "
+                 f"paths per iteration, point light and sphere occluder")
+    elif name == "merge":
+        ws = [G.config4(seed=4)]
+        specs = [[("merge", 4, it, 4_000_000)] for it in range(n)]
+        label = ("vertex merging at scale (config 4): 1920x1080 camera vertices, 4M light vertices per iteration "
+                 "with throughput and MIS partials")
+    else:
+        raise ValueError(name)
+    return ws, specs, label
 
 
-def _gen3(args):
-    seed, it, res, J, n = args
+def upload_batches(pool, specs):
+    from paper_2504_04411_amd.estimator import DevicePhotons
     from workloads import generators as G
-    return it, G.config3(seed, res=res, J=J, n_iter=n).photons(it)
+    flat = [s for it in specs for s in it]
+    gen = pool.map(G.batch, flat)
+    out = []
+    for it in specs:
+        out.append([DevicePhotons.upload(next(gen)) for _ in it])
+    return out
 
 
-def learned_vs_plain(args, ex):
+def run_leg(name, args, pool):
+    """Warm-up, autotune and R timed repeats of K iterations of one workload on the GPU."""
+    import torch
+    from paper_2504_04411_amd.estimator import Estimator
+    ws, specs, label = describe(name, args)
+    K, W, R = args.steps, args.warmup, args.repeats
+    t0 = time.perf_counter()
+    batches = upload_batches(pool, specs)
+    torch.cuda.synchronize()
+    print(f"# {name}: generated and uploaded {len(batches)} iterations of batches in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    p = ws[0].params
+    est = Estimator(p.r1, mode=p.mode, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    ids = list(range(len(ws)))
+    H = sum(w.kernels.n for w in ws)
+
+    def reset():
+        for s, w in enumerate(ws):
+            ks = w.kernels
+            est.set_kernels(s, ks.pos, ks.nrm, None, ks.cam_beta, ks.cam_mis, r1=w.params.r1, rmin=w.params.rmin)
+
+    reset()
+    est._workspace(max(est.workspace_for(b, ids) for b in batches))
+    fixed = args.tuning is not None
+    n_pre = W if (args.no_autotune or fixed) else max(W, min(args.tune_at, K) if args.tune_at >= 0 else K // 2)
+    for i in range(n_pre):
+        est.iterate(ids, batches[i % len(batches)])
+    torch.cuda.synchronize()
+    if fixed:
+        cs, hc, ll, lh = args.tuning.split(",")
+        est.set_tuning(float(cs), int(hc), int(ll), int(lh))
+    tuning = est.tuning()
+    if not (args.no_autotune or fixed):
+        tuning = est.autotune(ids, batches[n_pre % len(batches)])
+        print(f"# {name}: autotuned {tuning}", file=sys.stderr, flush=True)
+    reps = []
+    for r in range(R):
+        reset()
+        torch.cuda.synchronize()
+        est.profile(True)
+        t0 = time.perf_counter()
+        for i in range(K):
+            est.iterate(ids, batches[i])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = est.profile_read()
+        est.profile(False)
+        st = [est.stats(s) for s in ids]
+        reps.append(dict(dt=dt, prof=prof, pairs=sum(x["pairs"] for x in st), cand=sum(x["candidates"] for x in st)))
+    order = sorted(range(R), key=lambda i: reps[i]["dt"])
+    med = reps[order[R // 2]]
+    radii = np.concatenate([est.radii(s).cpu().numpy() for s in ids])
+    r1s = np.concatenate([np.full(w.kernels.n, np.float32(w.params.r1)) for w in ws])
+    prof = med["prof"]
+    gather_s = prof["gather_ms"] / 1e3
+    launch_ms = prof["gather_ms"] / max(prof["launches"], 1)
+    ops = OPS_PER_QUERY * H * K + OPS_PER_PAIR * med["pairs"]
+    alu = ops / gather_s / 1e12
+    J = sum(b.J for b in batches[0])
+    wl = WORKLOADS[name]
+    bytes_launch = J * wl["P_b"] + H * (wl["G_h"] + STATE_RW)
+    gbps = bytes_launch * prof["launches"] / K / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else 0.0
+    nrm = ws[0].kernels.nrm is not None
+    vcm = p.mode == "vcm"
+    kname = (f"gather_update_kernel<{str(nrm).lower()},{str(vcm).lower()},1,{tuning['lanes_light']},"
+             f"{tuning['lanes_heavy']}>")
+    traffic = profiled_traffic(name, kname, tuning)
+    alu_roof = {"bound": "alu", "achieved": round(alu, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(alu / VALU_PEAK_TOPS, 4),
+                "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
+    hbm_roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                "work_model": f"{wl['P_b']} B per light vertex + ({wl['G_h']} + {STATE_RW}) B per hit point per launch",
+                "algorithmic_bytes_per_launch": int(bytes_launch)}
+    out = {
+        "workload": label, "hit_points": H, "light_paths_per_iteration": int(J), "iterations": K,
+        "queries_per_s": round(H * K / med["dt"], 1), "ms_per_step": round(med["dt"] / K * 1e3, 4),
+        "repeats_ms_per_step": [round(x["dt"] / K * 1e3, 4) for x in reps],
+        "gather_test_update_queries_per_s": round(H * K / gather_s, 1),
+        "phase_ms_per_step": {"plan_and_grid": round(prof["grid_ms"] / K, 4),
+                              "fcrit_wait": round(prof["fcrit_wait_ms"] / K, 4),
+                              "work_list": round(prof["list_ms"] / K, 4),
+                              "gather_test_update": round(prof["gather_ms"] / K, 4),
+                              "tally": round(prof["tally_ms"] / K, 4)},
+        "tuning": dict(tuning, autotuned=not (args.no_autotune or fixed)),
+        "pairs_per_query": round(med["pairs"] / (H * K), 2),
+        "candidates_per_pair": round(med["cand"] / max(med["pairs"], 1), 3),
+        "final_radius": {"mean_over_r1": float((radii / r1s).mean()), "shrunk_frac": float((radii < r1s).mean())},
+        "dominant_kernel": {"kernel": kname, "avg_launch_ms": round(launch_ms, 4), "launches": int(prof["launches"])},
+        "alu_roofline": alu_roof, "hbm_roofline": hbm_roof, "traffic": traffic,
+    }
+    est.close()
+    del batches
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out, ws, specs
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes, timed with HIP events on the current stream: the achievable
+    read + write rate beside the published peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    t = statistics.median(ts)
+    return {"bytes": nbytes, "gbps_read_plus_write": round(2 * nbytes / t / 1e9, 1),
+            "frac_of_published": round(2 * nbytes / t / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
+def learned_vs_plain(args, pool):
     """The learned radius proposal against the plain method at equal MSE on jittered box scenes:
-    trained on seeds 30-33, margin picked on seed 34, compared on the held-out seed 39."""
+    trained on seeds 30-33, margin picked on seed 34, compared on the held-out seeds 39-43."""
     import torch
     from paper_2504_04411_amd import learned as Lr
     from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
@@ -83,96 +255,27 @@ def learned_vs_plain(args, ex):
 
     def make_scene(seed):
         w = G.config3(seed, res=res, J=J, n_iter=n)
-        out = [None] * n
-        for it, b in ex.map(_gen3, [(seed, i, res, J, n) for i in range(n)]):
-            out[it] = DevicePhotons.upload(b)
+        out = [DevicePhotons.upload(b) for b in pool.map(G.batch, [("jittered", seed, i, J, res) for i in range(n)])]
         return w, out
 
     p = G.config3(30, res=8, J=1000).params
     est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
-    out = Lr.experiment(est, make_scene, (30, 31, 32, 33), 34, 39,
+    out = Lr.experiment(est, make_scene, (30, 31, 32, 33), 34, tuple(range(39, 39 + args.learned_scenes)),
                         log=lambda m: print("# learned: " + m, file=sys.stderr, flush=True))
     est.close()
     torch.cuda.synchronize()
-    keep = {k: out[k] for k in ("plain_final_mse", "learned_final_mse", "iterations", "plain_ms", "learned_ms",
-                                "learned_iters_to_plain_final_mse", "learned_ms_to_plain_final_mse", "margin",
-                                "train_mse", "label_var", "train_rows")}
-    t = out["learned_ms_to_plain_final_mse"]
-    keep["speedup_to_plain_final_mse"] = round(out["plain_ms"] / t, 3) if t else None
+    keep = {k: out[k] for k in ("margin", "train_mse", "label_var", "train_rows", "train_steps", "train_gpu_ms",
+                                "features_gpu_ms", "summary")}
+    keep["scenes"] = [{k: r[k] for k in ("seed", "plain_final_mse", "learned_final_mse", "plain_ms",
+                                         "learned_iters_to_plain_final_mse", "learned_ms_to_plain_final_mse",
+                                         "speedup_to_plain_final_mse")} for r in out["scenes"]]
     keep["workload"] = (f"box scenes with jittered light and occluder, {res}x{res} hit points, {J} light paths per "
-                        f"iteration, {n} iterations; trained on seeds 30-33, margin from seed 34, compared on seed 39; "
-                        f"MSE of the radiance against the analytic direct light")
+                        f"iteration, {n} iterations; trained on seeds 30-33, margin from seed 34, compared on seeds "
+                        f"39-{38 + args.learned_scenes}; MSE of the radiance against the analytic direct light")
     return keep
 
 
-def _gen2(args):
-    s, it, J, edge, ca = args
-    from workloads import generators as G
-    return s, it, G.config2_photons(2, s, it, J, edge, ca)
-
-
-def batched_sets(args, ex, n_iter=8):
-    """Config 2 (16 independent planar sets of uneven size) through the batched launch: one
-    hk_iterate call for all sets per iteration, against one call per set, and the batched iteration
-    replayed from a captured graph against the same iteration run eagerly."""
-    import torch
-    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
-    from workloads import generators as G
-    meta = G.config2_sets(2)
-    ws = G.config2(seed=2, n_iter=n_iter)
-    n = len(ws)
-    batches = [[None] * n for _ in range(n_iter)]
-    jobs = [(s, it, J, edge, ca) for it in range(n_iter) for s, (_, J, edge, ca) in enumerate(meta)]
-    for s, it, b in ex.map(_gen2, jobs):
-        batches[it][s] = DevicePhotons.upload(b)
-    p = ws[0].params
-    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
-    ids = list(range(n))
-    H = sum(w.kernels.n for w in ws)
-
-    def reset():
-        for s, w in enumerate(ws):
-            est.set_kernels(s, w.kernels.pos, None, r1=w.params.r1, rmin=w.params.rmin)
-        est._workspace(max(est.workspace_for(bb, ids) for bb in batches))
-        torch.cuda.synchronize()
-
-    def timed(fn):
-        reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
-    reset()
-    tuning = est.tuning()
-    if not args.no_autotune:
-        for it in range(2):
-            est.iterate(ids, batches[it])
-        tuning = est.autotune(ids, batches[2 % n_iter])
-    out = {"workload": f"16 planar sets (config 2): {H} hit points and "
-                       f"{sum(m[1] for m in meta)} light paths per iteration in all, {n_iter} iterations",
-           "hit_points": H, "iterations": n_iter, "tuning": tuning}
-    t = timed(lambda: [est.iterate(ids, batches[it]) for it in range(n_iter)])
-    out["batched_queries_per_s"] = round(H * n_iter / t, 1)
-    t = timed(lambda: [est.iterate([s], [batches[it][s]]) for it in range(n_iter) for s in ids])
-    out["one_call_per_set_queries_per_s"] = round(H * n_iter / t, 1)
-    t = timed(lambda: [est.iterate(ids, batches[0]) for _ in range(n_iter)])
-    out["eager_repeated_batch_queries_per_s"] = round(H * n_iter / t, 1)
-    reset()
-    g = est.capture(ids, batches[0])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_iter):
-        g.launch()
-    torch.cuda.synchronize()
-    out["graph_repeated_batch_queries_per_s"] = round(H * n_iter / (time.perf_counter() - t0), 1)
-    g.close()
-    est.close()
-    return out
-
-
-def generated_end_to_end(args, w, tuning):
+def generated_end_to_end(args, tuning):
     """The box workload with its light vertices generated on the device: every iteration is one
     replay of a graph that writes the batch (hk_emit_box) and runs the estimator on it. The
     generation kernel alone is timed with HIP events on the stream it runs on; it writes 36 bytes
@@ -180,6 +283,8 @@ def generated_end_to_end(args, w, tuning):
     import torch
     from paper_2504_04411_amd import hk
     from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
+    from workloads import generators as G
+    w = G.config1(seed=args.seed, res=args.res, J=args.photons)
     p = w.params
     sc = w.info["scene"]
     power = float(np.float32(4.0 * math.pi * sc.intensity))
@@ -216,9 +321,8 @@ def generated_end_to_end(args, w, tuning):
     # vertex merging with the emission's partials, without and with the vertex connection to the
     # light (Eq. VCM-estimator), each one graph replay per iteration
     vcm = {}
-    Hn = w.kernels.n
-    ones = np.ones((3, Hn), np.float32)
-    zeros = np.zeros((3, Hn), np.float32)
+    ones = np.ones((3, H), np.float32)
+    zeros = np.zeros((3, H), np.float32)
     for connect in (False, True):
         ev = Estimator(p.r1, mode="vcm", k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
         ev.set_tuning(tuning["cell_scale"], tuning["heavy_cost"], tuning["lanes_light"], tuning["lanes_heavy"])
@@ -248,95 +352,144 @@ def generated_end_to_end(args, w, tuning):
                                   "work_model": "36 bytes written per slot"}}}
 
 
-def make_batches(seed, n, J, workers):
-    out = [None] * n
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        for it, b in ex.map(_gen, [(seed, i, J) for i in range(n)]):
-            out[it] = b
+def batched_vs_per_set(args, ws, specs, pool, tuning):
+    """The headline sets run as one batched call per iteration against one call per set, and a
+    captured graph of one batched iteration replayed against the same iteration run eagerly."""
+    import torch
+    from paper_2504_04411_amd.estimator import Estimator
+    n_it = min(args.steps, 8)
+    batches = upload_batches(pool, specs[:n_it])
+    p = ws[0].params
+    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
+    est.set_tuning(tuning["cell_scale"], tuning["heavy_cost"], tuning["lanes_light"], tuning["lanes_heavy"])
+    ids = list(range(len(ws)))
+    H = sum(w.kernels.n for w in ws)
+
+    def reset():
+        for s, w in enumerate(ws):
+            est.set_kernels(s, w.kernels.pos, None, r1=w.params.r1, rmin=w.params.rmin)
+        est._workspace(max(est.workspace_for(b, ids) for b in batches))
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        reset()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    out = {"iterations": n_it}
+    out["batched_queries_per_s"] = round(H * n_it / timed(lambda: [est.iterate(ids, batches[i]) for i in range(n_it)]), 1)
+    out["one_call_per_set_queries_per_s"] = round(
+        H * n_it / timed(lambda: [est.iterate([s], [batches[i][s]]) for i in range(n_it) for s in ids]), 1)
+    out["eager_repeated_batch_queries_per_s"] = round(
+        H * n_it / timed(lambda: [est.iterate(ids, batches[0]) for _ in range(n_it)]), 1)
+    reset()
+    g = est.capture(ids, batches[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_it):
+        g.launch()
+    torch.cuda.synchronize()
+    out["graph_repeated_batch_queries_per_s"] = round(H * n_it / (time.perf_counter() - t0), 1)
+    g.close()
+    est.close()
+    del batches
+    torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(w, batches, stride, nthreads):
-    """The oracle as it stands (grid mode, OpenMP over kernels) on every `stride`-th kernel for all
-    iterations; returns queries/s of that sample."""
+def cpu_baseline(args, pool, ws, specs):
+    """The oracle as it stands (grid mode, OpenMP over hit points) on a sample of the headline
+    workload: every `stride`-th hit point of every set for the first `iters` iterations. The oracle
+    builds each set's grid over all of the set's light vertices whatever the sample, so the sample is
+    charged its share of that build (the build time of a one-hit-point gather, times the sampled
+    fraction) plus its own gather and update. Returns queries/s on `threads` threads."""
     from oracle import oracle as O
-    idx = np.arange(0, w.kernels.n, stride)
-    ks = w.kernels.subset(idx)
-    st = O.init_state(idx.size, w.params.r1)
-    O.f_critical(np.array([b.J * (i + 1) for i, b in enumerate(batches)], float), w.params.alpha_f)  # warm cache
-    t0 = time.perf_counter()
-    for b in batches:
-        O.iterate(w.params, ks, st, b, use_grid=True, nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    return idx.size * len(batches) / dt, dt, idx.size
+    from workloads import generators as G
+    iters = args.cpu_iters
+
+    def run(threads, stride, n_it):
+        subs = []
+        for w in ws:
+            idx = np.arange(0, w.kernels.n, stride)
+            subs.append((w, w.kernels.subset(idx), w.kernels.subset(np.array([0])), idx.size / w.kernels.n))
+        states = [O.init_state(ks.n, w.params.r1) for w, ks, _, _ in subs]
+        ones = [O.init_state(1, w.params.r1) for w, _, _, _ in subs]
+        flat = [s for it in specs[:n_it] for s in it]
+        gen = pool.map(G.batch, flat)
+        t_sample = t_grid_share = t_update = 0.0
+        for it in range(n_it):
+            for s, (w, ks, k1, frac) in enumerate(subs):
+                ph = next(gen)
+                O.f_critical(np.array([ph.J * (t + 1) for t in range(it + 1)], float), w.params.alpha_f)
+                t0 = time.perf_counter()
+                g = O.gather(ks, ph, states[s].r, use_grid=True, nthreads=threads)
+                t1 = time.perf_counter()
+                O.gather(k1, ph, ones[s].r, use_grid=True, nthreads=threads)
+                t2 = time.perf_counter()
+                O.iterate(w.params, ks, states[s], ph, gathered=g)
+                t3 = time.perf_counter()
+                t_sample += t1 - t0
+                t_grid_share += (t2 - t1) * (1.0 - frac)
+                t_update += t3 - t2
+        nq = sum(ks.n for _, ks, _, _ in subs) * n_it
+        charged = max(t_sample - t_grid_share, 1e-9) + t_update
+        return nq / charged, charged, nq
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    q, secs, nq = run(threads, args.cpu_stride, iters)
+    q1, secs1, nq1 = run(1, args.cpu_stride * 8, 1)
+    return {"value": round(q, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"oracle grid mode on one hit point in {args.cpu_stride} of each of the 16 sets ({nq // iters} "
+                      f"hit points) for the first {iters} iterations of the same inputs, {secs:.1f}s charged "
+                      f"(the sample's share of each set's grid build, its gather and its update)",
+            "one_core": {"value": round(q1, 1), "sample": f"one hit point in {args.cpu_stride * 8}, first iteration "
+                                                          f"({nq1} queries), {secs1:.1f}s charged"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--photons", type=int, default=2_000_000)
-    ap.add_argument("--res", type=int, default=512)
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=20, help="timed iterations per repeat (K)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed iterations before the autotuner (W)")
+    ap.add_argument("--repeats", type=int, default=5, help="timed repeats per workload; the median is reported")
+    ap.add_argument("--photons", type=int, default=2_000_000, help="box scene: light paths per iteration")
+    ap.add_argument("--res", type=int, default=512, help="box scene: hit points per side")
+    ap.add_argument("--seed", type=int, default=1, help="box scene seed")
+    ap.add_argument("--only", choices=["sets", "box", "merge"], default=None,
+                    help="measure one workload only (profiling runs); it becomes the printed value")
+    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--learned-scenes", type=int, default=5, help="held-out scenes of the learned comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-generated", action="store_true", help="skip the device-generated box run")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
     ap.add_argument("--tuning", default=None, metavar="CELL,HEAVY,LANES_LIGHT,LANES_HEAVY",
                     help="fixed tuning instead of the autotuner (profiling runs pin the autotuned setting)")
-    ap.add_argument("--tune-at", type=int, default=32,
-                    help="untimed iterations before the autotuner samples the state")
-    ap.add_argument("--no-batched", action="store_true", help="skip the many-set (config 2) measurement")
-    ap.add_argument("--no-generated", action="store_true",
-                    help="skip the run with light vertices generated on the device")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--tune-at", type=int, default=-1,
+                    help="untimed iterations before the autotuner samples the state (default: K / 2, the middle "
+                         "of the timed run; at least W)")
+    ap.add_argument("--workers", type=int, default=15, help="batch-generating worker processes (<= 15)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="before the timed job, copy a MIB-sized device buffer once (reference for HBM "
-                         "traffic counters: it reads and writes exactly MIB MiB)")
+                    help="before the legs, copy a MIB-sized device buffer once (reference for HBM traffic "
+                         "counters: it reads and writes exactly MIB MiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described but "
               "not built", file=sys.stderr)
         sys.exit(2)
 
+    # the batch generators run in spawned processes, started before anything touches the GPU
+    from workloads import generators as G
+    pool = G.spawn_pool(min(max(args.workers, 1), 15))
+
     import torch
     from paper_2504_04411_amd import hk
-    from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
-    from workloads import generators as G
-
     hk.lib()
     torch.cuda.set_device(0)
-    w = G.config1(seed=args.seed, res=args.res, J=args.photons)
-    K, W = args.steps, args.warmup
-    t0 = time.perf_counter()
-    batches = make_batches(args.seed, max(K, W), args.photons, args.workers)
-    print(f"# generated {len(batches)} batches in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    dev = [DevicePhotons.upload(b) for b in batches]
-    torch.cuda.synchronize()
-
-    p = w.params
-    est = Estimator(p.r1, k=p.k, alpha_f=p.alpha_f, alpha=p.alpha, rmin=p.rmin)
-    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)
-    # untimed warm-up; the autotuner samples the state after `tune_at` iterations (the middle of the
-    # timed run: at iteration 16 it preferred cells of 1.0 r, 2% slower than 0.7 r over 64 iterations),
-    # then the timed run restarts from a fresh state
-    fixed = args.tuning is not None
-    n_pre = W if (args.no_autotune or fixed) else max(W, args.tune_at)
-    for i in range(n_pre):
-        est.iterate([0], [dev[i % len(dev)]])
-    torch.cuda.synchronize()
-    if fixed:
-        cs, hc, ll, lh = args.tuning.split(",")
-        est.set_tuning(float(cs), int(hc), int(ll), int(lh))
-    tuning = est.tuning()
-    if not (args.no_autotune or fixed):
-        # settings timed on scratch copies of the warmed-up state with the next batch
-        tuning = est.autotune([0], [dev[n_pre % len(dev)]])
-        print(f"# autotuned: {tuning}", file=sys.stderr, flush=True)
-    est.set_kernels(0, w.kernels.pos, w.kernels.nrm)         # fresh state for the timed job
-    est._workspace(max(est.workspace_for([d], [0]) for d in dev))
-    torch.cuda.synchronize()
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -345,59 +498,39 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    est.profile(True)
-    t0 = time.perf_counter()
-    for i in range(K):
-        est.iterate([0], [dev[i]])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = est.profile_read()
-    stats = est.stats(0)
-    radii = est.radii(0).cpu().numpy()
-    H = w.kernels.n
-    value = H * K / dt
-    gather_s = prof["gather_ms"] / 1e3
-    launch_ms = prof["gather_ms"] / max(prof["launches"], 1)
-    ops = OPS_PER_QUERY * H * K + OPS_PER_PAIR * stats["pairs"]
-    achieved = ops / gather_s / 1e12
-    kname = f"gather_update_kernel<true,false,1,{tuning['lanes_light']},{tuning['lanes_heavy']}>"
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": profiled_traffic(kname, tuning),
-            "kernel": kname, "avg_launch_ms": round(launch_ms, 4),
-            "work_model": "150 ops/query + 58.2 ops/in-disk pair (VALU lane ops)"}
+    head = args.only or "sets"
+    legs = [head] if args.only else ["sets", "box", "merge"]
+    res = {}
+    for name in legs:
+        res[name] = run_leg(name, args, pool)
+    main_out, ws, specs = res[head]
+    dom = main_out["dominant_kernel"]
+    roof = dict(main_out["alu_roofline"] if head != "merge" else main_out["hbm_roofline"])
+    roof.update(traffic=main_out["traffic"], kernel=dom["kernel"], avg_launch_ms=dom["avg_launch_ms"])
     out = {
         "metric": "photon-kernel queries/sec (gather+F-test+update) at 1 GPU",
-        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": round(dt / K * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"box scene, {args.res}x{args.res} hit points with normals, {args.photons} photons "
-                               f"per iteration, point light and sphere occluder, {K} iterations",
-                   "H": H, "J": args.photons, "iterations": K, "seed": args.seed},
-        "gather_test_update_queries_per_s": round(H * K / gather_s, 1),
-        "phase_ms_total": {"plan_and_grid": round(prof["grid_ms"], 3), "fcrit_wait": round(prof["fcrit_wait_ms"], 3),
-                           "work_list": round(prof["list_ms"], 3), "gather_test_update": round(prof["gather_ms"], 3),
-                           "tally": round(prof["tally_ms"], 3)},
-        "tuning": dict(tuning, autotuned=not (args.no_autotune or fixed)),
-        "pairs_per_query": round(stats["pairs"] / (H * K), 2),
-        "candidates_per_pair": round(stats["candidates"] / max(stats["pairs"], 1), 3),
-        "final_radius": {"mean": float(radii.mean()), "min": float(radii.min()),
-                         "shrunk_frac": float((radii < np.float32(p.r1)).mean())},
+        "value": main_out["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_out["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": main_out["workload"], "hit_points": main_out["hit_points"],
+                   "light_paths_per_iteration": main_out["light_paths_per_iteration"], "iterations": args.steps,
+                   "repeats": args.repeats, "statistic": "median of the repeats"},
         "roofline": roof,
+        head: {k: v for k, v in main_out.items() if k not in ("workload",)},
     }
-    if not args.no_generated:
-        out["generated_end_to_end"] = generated_end_to_end(args, w, tuning)
-    if not args.no_batched:
-        with ProcessPoolExecutor(max_workers=args.workers) as ex:
-            out["batched_sets"] = batched_sets(args, ex)
-    if not args.no_learned:
-        with ProcessPoolExecutor(max_workers=args.workers) as ex:
-            out["learned_vs_plain"] = learned_vs_plain(args, ex)
-    if not args.no_cpu_baseline:
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        q, secs, nk = cpu_baseline(w, batches[:K], args.cpu_stride, nthreads)
-        out["cpu_baseline"] = {"value": round(q, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-                               "sample": f"oracle grid mode on every {args.cpu_stride}th hit point ({nk} kernels) "
-                                         f"for all {K} iterations of the same inputs, {secs:.1f}s"}
+    for name in legs:
+        if name != head:
+            out[name] = res[name][0]
+    out["copy_bandwidth"] = copy_bandwidth()
+    if not args.only:
+        out["sets"]["batched_vs_per_set"] = batched_vs_per_set(args, ws, specs, pool, res["sets"][0]["tuning"])
+        if not args.no_generated:
+            out["generated_end_to_end"] = generated_end_to_end(args, res["box"][0]["tuning"])
+        if not args.no_learned:
+            out["learned_vs_plain"] = learned_vs_plain(args, pool)
+    if not args.no_cpu_baseline and head == "sets":
+        out["cpu_baseline"] = cpu_baseline(args, pool, ws, specs)
+    pool.shutdown()
     print(json.dumps(out), flush=True)
 
 

@@ -231,37 +231,75 @@ def he_init(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def experiment(est: Estimator, make_scene, train_seeds, val_seed, test_seed, margins=(0.0, 0.5, 1.0, 1.5),
+def experiment(est: Estimator, make_scene, train_seeds, val_seed, test_seeds, margins=(0.0, 0.5, 1.0, 1.5),
                epoch_blocks: int = 4, epochs_per_block: int = 3, batch: int = 8192, lr: float = 2e-3,
                init_seed: int = 1, log=None):
     """Trains a network on plain runs of the training scenes (features at iterations 1, 2, 4, 8 ->
     log(r_final / r1)), picks the proposal margin on the validation scene, and compares plain and
-    learned runs of the test scene at equal MSE. make_scene(seed) -> (workload, device batches)."""
+    learned runs of each held-out test scene at equal MSE. make_scene(seed) -> (workload, device
+    batches). The top-level comparison fields are those of the first test scene; `scenes` lists
+    every test scene and `summary` their mean and spread; `train_gpu_ms` is the GPU time of the
+    training steps (gradient and Adam kernels), `features_gpu_ms` that of building the training rows
+    (plain runs included)."""
     say = log or (lambda *a: None)
+    seeds = [test_seeds] if isinstance(test_seeds, int) else list(test_seeds)
     X, Y = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    feat_ms = 0.0
     for s in train_seeds:
         sc = make_scene(s)
+        e0.record()
         x, y = training_set(est, [sc])
+        e1.record()
+        torch.cuda.synchronize()
+        feat_ms += e0.elapsed_time(e1)
         X.append(x)
         Y.append(y)
         del sc
         say(f"training scene {s}: {x.shape[0]} rows")
     X, Y = torch.cat(X).contiguous(), torch.cat(Y).contiguous()
     net = Network(est, he_init(init_seed))
+    e0.record()
+    steps = 0
     for b in range(epoch_blocks):
         f = 0.4 ** b
-        net.train(X, Y, epochs=epochs_per_block, batch=min(batch, X.shape[0]), lr=lr * f, seed=b, lr_final=0.5 * lr * f)
+        steps += net.train(X, Y, epochs=epochs_per_block, batch=min(batch, X.shape[0]), lr=lr * f, seed=b,
+                           lr_final=0.5 * lr * f)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
     _, sq = net.grad(X, Y)
     rows = int(X.shape[0])
     train_mse, label_var = sq / rows, float(Y.var())
-    say(f"trained: mse {train_mse:.4f} against label variance {label_var:.4f}")
+    say(f"trained: mse {train_mse:.4f} against label variance {label_var:.4f} ({steps} steps, {train_ms:.1f} ms)")
     del X, Y
     wv, bv = make_scene(val_seed)
     margin, val = choose_margin(est, net, wv, bv, truth_box(wv), margins)
     del bv
     say(f"margin {margin} chosen on scene {val_seed}")
-    wt, bt = make_scene(test_seed)
-    out = compare(est, net, wt, bt, truth_box(wt), margin=margin)
-    out.update(margin=margin, train_mse=train_mse, label_var=label_var, train_rows=rows)
+    scenes = []
+    for s in seeds:
+        wt, bt = make_scene(s)
+        r = compare(est, net, wt, bt, truth_box(wt), margin=margin)
+        del bt
+        t = r["learned_ms_to_plain_final_mse"]
+        r["speedup_to_plain_final_mse"] = (r["plain_ms"] / t) if t else None
+        r["seed"] = s
+        scenes.append(r)
+        say(f"scene {s}: plain final MSE {r['plain_final_mse']:.3e}, learned reaches it at iteration "
+            f"{r['learned_iters_to_plain_final_mse']} ({r['speedup_to_plain_final_mse']})")
+    out = dict(scenes[0])
+    out.update(margin=margin, train_mse=train_mse, label_var=label_var, train_rows=rows, train_steps=steps,
+               train_gpu_ms=train_ms, features_gpu_ms=feat_ms)
     out["validation"] = {str(m): {k: v for k, v in r.items()} for m, r in val.items()}
+    out["scenes"] = scenes
+    sp = [r["speedup_to_plain_final_mse"] for r in scenes if r["speedup_to_plain_final_mse"]]
+    its = [r["learned_iters_to_plain_final_mse"] for r in scenes if r["learned_iters_to_plain_final_mse"]]
+    out["summary"] = {
+        "test_scenes": len(scenes), "reached": len(sp),
+        "speedup_mean": float(np.mean(sp)) if sp else None, "speedup_min": float(min(sp)) if sp else None,
+        "speedup_max": float(max(sp)) if sp else None, "speedup_std": float(np.std(sp)) if sp else None,
+        "iterations_mean": float(np.mean(its)) if its else None,
+        "iterations_min": int(min(its)) if its else None, "iterations_max": int(max(its)) if its else None,
+    }
     return out

@@ -1,5 +1,5 @@
 """Host-side logic of the benchmark (CPU): the one-GPU guard and the rule that HBM traffic is reported
-only from a profile of the same kernel sources, instance and tuning."""
+only from a profile of the same workload, kernel sources, instance and tuning."""
 import hashlib
 import json
 import os
@@ -19,12 +19,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def _record(tmp_path, sha, instance, tuning):
+def _record(tmp_path, sha, instance, tuning, workload="box"):
     d = tmp_path / "profiles"
     d.mkdir()
-    rec = {"kernel": "gather_update_kernel", "instance": instance, "tuning": tuning, "source_sha256_16": sha,
-           "avg_launch_ms": 1.0, "traffic_bytes_per_launch": 123456}
-    (d / "gather_update_box.md").write_text("# profile\n\n```\n" + json.dumps(rec) + "\n```\n")
+    rec = {"kernel": "gather_update_kernel", "workload": workload, "instance": instance, "tuning": tuning,
+           "source_sha256_16": sha, "avg_launch_ms": 1.0, "traffic_bytes_per_launch": 123456}
+    (d / "gather_traffic.md").write_text("# profile\n\n```\n" + json.dumps(rec) + "\n```\n")
 
 
 def _sources_sha():
@@ -51,10 +51,11 @@ def test_traffic_only_for_the_profiled_sources_instance_and_tuning(tmp_path, ben
         (tmp_path / "paper_2504_04411_amd" / "csrc" / f).write_bytes(
             open(os.path.join(ROOT, "paper_2504_04411_amd", "csrc", f), "rb").read())
     monkeypatch.setattr(bench_mod, "ROOT", str(tmp_path))
-    assert bench_mod.profiled_traffic(inst, tun) == 123456
-    assert bench_mod.profiled_traffic("gather_update_kernel<true,false,1,8,64>", tun) is None
-    assert bench_mod.profiled_traffic(inst, dict(tun, heavy_cost=4096)) is None
+    assert bench_mod.profiled_traffic("box", inst, tun) == 123456
+    assert bench_mod.profiled_traffic("sets", inst, tun) is None
+    assert bench_mod.profiled_traffic("box", "gather_update_kernel<true,false,1,8,64>", tun) is None
+    assert bench_mod.profiled_traffic("box", inst, dict(tun, heavy_cost=4096)) is None
     # a changed source invalidates the record
     p = tmp_path / "paper_2504_04411_amd" / "csrc" / "hk_gather.hip"
     p.write_bytes(p.read_bytes() + b"\n")
-    assert bench_mod.profiled_traffic(inst, tun) is None
+    assert bench_mod.profiled_traffic("box", inst, tun) is None
