@@ -1110,11 +1110,13 @@ __global__ void read_sums_kernel(StateView st, int64_t n, double *S, double *Q, 
     if (s >= n) return;
     const uint32_t j = st.orig[s];
     const size_t a = st.astride;
-    const float *sq = st.sq0 + s, *tv = st.tau0 + s;
+    const float *tv = st.tau0 + s;
     const int w = NG * st.nch;                  // columns: channel * NG + group
+    const float4 *sq = st.sq4 + (size_t)s * w;
     for (int g = 0; g < w; ++g) {
-        if (S) S[(int64_t)j * w + g] = (double)sq[(4 * g) * a] + (double)sq[(4 * g + 1) * a];
-        if (Q) Q[(int64_t)j * w + g] = (double)sq[(4 * g + 2) * a] + (double)sq[(4 * g + 3) * a];
+        const float4 x = sq[g];
+        if (S) S[(int64_t)j * w + g] = (double)x.x + (double)x.y;
+        if (Q) Q[(int64_t)j * w + g] = (double)x.z + (double)x.w;
     }
     if (tau)
         for (int c = 0; c < 3; ++c) tau[(int64_t)j * 3 + c] = (double)tv[(2 * c) * a] + (double)tv[(2 * c + 1) * a];

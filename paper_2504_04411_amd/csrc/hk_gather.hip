@@ -4,16 +4,14 @@
 // Work decomposition: G lanes of a wavefront serve one kernel (hit point). The kernel's grid
 // stencil (cells overlapping the box [x - r, x + r], grown by a rounding margin) is a list of rows
 // of cells; with x fastest each row is a contiguous range of the sorted photon payload, clipped to
-// the x-range that can reach the disk. The G lanes walk the concatenated rows G photons at a time
-// (coalesced 16-byte loads, eight in flight per lane), test their photon against the disk and
-// accumulate into lane-private compensated sums kept in LDS. At the end the G partial results are
-// combined in a fixed order (deterministic) and the kernel's epilogue runs.
-//
-// The test and the accumulation are decoupled: each step tests G candidates (one per lane), the
-// in-disk ones are queued in LDS (stream order) and later accumulated up to 2G at a time by the
-// kernel's G lanes together, so the accumulation runs with every lane busy instead of only the
-// third of lanes whose candidate fell inside the disk. Lane j always takes the in-disk photons at
-// stream positions congruent to j mod G, so the sums do not depend on the other kernels of the wave.
+// the x-range that can reach the disk. The G lanes walk the concatenated rows G photons at a time:
+// lane j takes the candidates at positions j, j + G, ... of the concatenation, loads each one's whole
+// payload (16-byte loads, four candidates in flight per lane), tests it against the disk and, when
+// it is inside, adds it at once to lane-private compensated sums kept in LDS. Each lane thus sums a
+// fixed subsequence of the kernel's candidates, so a kernel's sums never depend on the other kernels
+// of its wave; at the end the G partial results are combined in a fixed order (deterministic) and
+// the kernel's epilogue runs. Nothing waits between the test and the accumulation: the only memory
+// round trips of a kernel are its rows' cell starts, its candidates and its state.
 //
 // Light kernels share a wave (16 lanes each as tuned); kernels whose expected candidate count
 // exceeds `heavy_cost` get a whole wave and are listed first, so the longest work starts first. The
@@ -85,20 +83,16 @@ __device__ __forceinline__ float4 ldb(const float4 *base, uint32_t off)
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
-constexpr int UNROLL = 8;         // candidate loads in flight per lane
+constexpr int UNROLL_D = 4;       // candidates (all their payload) in flight per lane
 constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 
-constexpr int DRAIN = 2;           // photons per lane per drain (their loads are issued together)
-constexpr int QCAP = DRAIN + 1;    // queue capacity per kernel, in multiples of its G lanes
-
-// 13.25 KB per wavefront with one test channel (12 wavefronts per CU; the register budget allows
-// 12 as well); 37.25 KB with one test per RGB channel.
+// 12.5 KB per wavefront with one test channel (12 wavefronts per CU); 36.5 KB with one test per RGB
+// channel.
 template <int CH>
 struct Lds {
     float4 slot[NG * CH][WAVE];   // lane-private pairs (S, err S, Q, err Q) per channel and group
     uint32_t dl[WAVE];            // row start, byte offset into the position plane
     uint32_t re[WAVE];            // row end (exclusive), byte offset into the position plane
-    uint32_t queue[QCAP * WAVE];  // in-disk photons waiting for accumulation: 3 G per kernel
 };
 
 // Per-kernel constants of one work item, held in registers by the kernel's G lanes.
@@ -124,12 +118,12 @@ struct Acc {
     uint32_t cnt;
 };
 
-// The payload of one queued photon: position and luminance, normal and dVM, flux and dVCM.
+// The payload of one candidate: position and luminance, normal and dVM, flux and dVCM.
 struct Cand {
     float4 a, b, f;
 };
 
-// A queued photon is held as the byte offset of its plane-A entry; its (B, C) pair lies at twice that
+// A candidate is addressed by the byte offset of its plane-A entry; its (B, C) pair lies at twice that
 // offset from the pair plane's base.
 template <bool NRM, bool VCM>
 __device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rA, const float4 *rBC)
@@ -142,11 +136,10 @@ __device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rA, const 
     return P;
 }
 
-// Adds a queued photon (already inside the disk) to this lane's group sums and flux sum when it
-// passes the normal-consistency test. The distance vector is recomputed from the payload with the
-// same float32 operations as in the test, so the values are those the test saw. A photon that
-// fails the normal test is added as zeros (an exact no-op on the pairs), so its loads never wait on
-// the test.
+// Adds a candidate found inside the disk to this lane's group sums and flux sum when it passes the
+// normal-consistency test. The distance vector is recomputed with the same float32 operations as
+// in the test, so the values are those the test saw. A photon that fails the normal test is added
+// as zeros (an exact no-op on the pairs).
 template <bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float cos_min, Lds<CH> &L, int lane,
                                            Acc &c)
@@ -202,43 +195,6 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
     kahan(c.fG, c.cG, wG);
     kahan(c.fB, c.cB, wB);
     c.cnt += ok ? 1u : 0u;
-}
-
-// Each kernel's queue holds up to QCAP G entries from its start; `head` counts the kernel's photons
-// accumulated so far, mod G. A drain takes from every kernel whatever it holds, up to DRAIN G
-// photons: lane j takes the photons whose positions in the kernel's in-disk stream are congruent to
-// j mod G, in stream order, so every lane sums a fixed subsequence of the stream whatever the drain
-// times and sizes (which depend on the other kernels of the wave), and the result of a kernel does
-// not depend on its neighbours in the launch. Taking the partial queues of the other kernels too
-// keeps them from triggering drains of their own soon after, so fewer drains run with idle lanes.
-// The loads of a lane's photons are issued together, then the photons are added in order. Drains
-// are called when some kernel holds DRAIN G photons (less than QCAP G); afterwards every kernel holds
-// fewer than G, moved to the front of its queue, so a step's push (at most G) appends without
-// wrapping and never overwrites a queued photon.
-template <int G, bool NRM, bool VCM, int CH>
-__device__ __forceinline__ void drain_once(uint32_t &qlen, uint32_t &head, int j, int base,
-                                           const Query &K, float cos_min, const float4 *rA, const float4 *rBC,
-                                           Lds<CH> &L, int lane, Acc &c)
-{
-    __syncthreads();
-    const uint32_t n = (qlen < (uint32_t)(DRAIN * G)) ? qlen : (uint32_t)(DRAIN * G);
-    const uint32_t k = ((uint32_t)j - head) & (uint32_t)(G - 1);
-    Cand P[DRAIN];
-#pragma unroll
-    for (int i = 0; i < DRAIN; ++i)
-        if (k + (uint32_t)(i * G) < n)
-            P[i] = load_cand<NRM, VCM>(L.queue[QCAP * base + k + (uint32_t)(i * G)], rA, rBC);
-    // the remainder (fewer than G, only when DRAIN G were taken) moves to the front: its entries
-    // lie at or beyond DRAIN G, its new places below G, and every read above precedes the writes
-    const uint32_t rest = qlen - n;
-    uint32_t mv = 0u;
-    if ((uint32_t)j < rest) mv = L.queue[QCAP * base + n + (uint32_t)j];
-    if ((uint32_t)j < rest) L.queue[QCAP * base + (uint32_t)j] = mv;
-#pragma unroll
-    for (int i = 0; i < DRAIN; ++i)
-        if (k + (uint32_t)(i * G) < n) accumulate<NRM, VCM, CH>(P[i], K, cos_min, L, lane, c);
-    qlen = rest;
-    head = (head + n) & (uint32_t)(G - 1);
 }
 
 template <int G, bool NRM, bool VCM, int CH>
@@ -300,7 +256,6 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 #pragma unroll
     for (int g = 0; g < NG * CH; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
-    uint32_t qlen = 0, head = 0;
     uint32_t ncand = 0;                           // candidate tests of this kernel (all row batches)
 
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
@@ -335,19 +290,18 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         // Per-lane cursor over the concatenated rows, as a byte offset into plane A: lane j takes the
         // photons at positions j, j + G, ... of the concatenation. Passing a row's end carries the
         // overshoot into the next row; past the last non-empty row the cursor rests on the point at
-        // infinity. Loads are issued U steps at a time (U independent loads in flight per lane), then
-        // the U candidates are tested from registers; those inside the disk are queued.
+        // infinity. The payloads of U steps are loaded together (U candidates in flight per lane),
+        // then the U candidates are tested from registers and those inside the disk accumulated.
         const uint64_t nonempty = __ballot(len > 0u) & gmask;
         const int last = nonempty ? (63 - __clzll((long long)nonempty)) - base : -1;
         int cur = 0;
         uint32_t end = L.re[base];
         uint32_t off = L.dl[base] + ((uint32_t)j << 4);
         uint32_t stride = (uint32_t)G << 4;
-        for (int s0 = 0; s0 < nsteps; s0 += UNROLL) {
-            float4 a[UNROLL];
-            uint32_t offs[UNROLL];
+        for (int s0 = 0; s0 < nsteps; s0 += UNROLL_D) {
+            Cand P[UNROLL_D];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
+            for (int u = 0; u < UNROLL_D; ++u) {
                 while (off >= end) {
                     if (++cur > last) {
                         off = sent;
@@ -358,42 +312,33 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                         end = L.re[base + cur];
                     }
                 }
-                offs[u] = off;
-                a[u] = ldb(rA, off);
+                P[u] = load_cand<NRM, VCM>(off, rA, rBC);
                 off += stride;
             }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const float dx = K.p[0] - a[u].x, dy = K.p[1] - a[u].y, dz = K.p[2] - a[u].z;
+            for (int u = 0; u < UNROLL_D; ++u) {
+                const float dx = K.p[0] - P[u].a.x, dy = K.p[1] - P[u].a.y, dz = K.p[2] - P[u].a.z;
                 const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const bool in = d2 < K.r2;
-                // queue the in-disk photons of this step in lane order: the kernel's lanes of the
-                // ballot, counted below this lane and in all
-                const uint64_t mk = __ballot(in) & gmask;
-                const uint32_t before =
-                    __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                if (in) L.queue[QCAP * base + qlen + before] = offs[u];
-                qlen += (uint32_t)__popcll(mk);
-                if (__ballot(qlen >= (uint32_t)(DRAIN * G)) != 0ull)
-                    drain_once<G, NRM, VCM, CH>(qlen, head, j, base, K, A.cos_min, rA, rBC, L, lane, c);
+                if (d2 < K.r2) accumulate<NRM, VCM, CH>(P[u], K, A.cos_min, L, lane, c);
             }
         }
     }
-    // The epilogue's state reads are issued before the last drains, so their latency overlaps them:
-    // the retained sums of the lane's columns, the kept-iteration count's J sums and critical
-    // value, and (first lane) the photons seen and the running estimate.
+    // The epilogue's state reads: the retained sums of the lane's columns, the kept-iteration
+    // count's J sums and critical value, and (first lane) the photons seen and the running estimate.
     constexpr int COLS = NG * CH;                 // column = channel * NG + group
     constexpr int CPL = (COLS + G - 1) / G;
+    float4 *const sq4 = reinterpret_cast<float4 *>(fslot(SL_SQ));   // per hit point, COLS float4s
     float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
         S[k] = cS[k] = Q[k] = cQ[k] = 0.0f;
         if (active && col < COLS) {
-            S[k] = fslot(SL_SQ + 4 * col)[q];
-            cS[k] = fslot(SL_SQ + 4 * col + 1)[q];
-            Q[k] = fslot(SL_SQ + 4 * col + 2)[q];
-            cQ[k] = fslot(SL_SQ + 4 * col + 3)[q];
+            const float4 x = sq4[(size_t)q * COLS + col];
+            S[k] = x.x;
+            cS[k] = x.y;
+            Q[k] = x.z;
+            cQ[k] = x.w;
         }
     }
     const uint32_t t_new = t_prev + 1u;
@@ -405,8 +350,6 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 #pragma unroll
     for (int cc = 0; cc < 6; ++cc) tv[cc] = lead ? fslot(SL_TAU + cc)[q] : 0.0f;
 
-    while (__ballot(qlen > 0u) != 0ull)
-        drain_once<G, NRM, VCM, CH>(qlen, head, j, base, K, A.cos_min, rA, rBC, L, lane, c);
     __syncthreads();
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
@@ -527,12 +470,9 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
-        if (active && col < COLS) {
-            fslot(SL_SQ + 4 * col)[q] = shrink ? 0.0f : S[k];
-            fslot(SL_SQ + 4 * col + 1)[q] = shrink ? 0.0f : cS[k];
-            fslot(SL_SQ + 4 * col + 2)[q] = shrink ? 0.0f : Q[k];
-            fslot(SL_SQ + 4 * col + 3)[q] = shrink ? 0.0f : cQ[k];
-        }
+        if (active && col < COLS)
+            sq4[(size_t)q * COLS + col] = shrink ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
+                                                 : make_float4(S[k], cS[k], Q[k], cQ[k]);
     }
     __syncthreads();
 }
@@ -680,7 +620,7 @@ __global__ __launch_bounds__(256) void split_kernel(const uint32_t *cost, const 
 {
     constexpr int PER = SPLIT_TILE / 256;
     // the payload's last position entry: a point at infinity, the gather's stand-in once a lane has
-    // walked past its kernel's last row (outside every disk, never queued)
+    // walked past its kernel's last row (outside every disk, never accumulated)
     if (blockIdx.x == 0 && threadIdx.x == 0) *sentinel = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     // heavy entries of the tiles before this one, summed by the whole block
     uint32_t hb = 0;

@@ -100,7 +100,8 @@ struct StateView {
     float *r;
     uint32_t *t, *nseen, *orig, *cnt, *dec;
     uint32_t *cand;      // candidate tests of the last iteration (the next work list's cost estimate)
-    float *sq0;          // group sums: array k at sq0 + k * astride, NSQ * nch arrays
+    float *sq0;          // group sums: NSQ * nch slots holding, per hit point s, NG * nch float4s
+    float4 *sq4;         // (S, err S, Q, err Q) at sq4[s * NG * nch + column], column = channel * NG + group
     int nch;             // test channels
     float *tau0;         // estimate: array c at tau0 + c * astride
     uint32_t astride;    // floats between slots
@@ -133,6 +134,7 @@ inline StateView make_view(void *base, const Layout &L)
     s.dec = u(SL_DEC);
     s.cand = u(SL_CAND);
     s.sq0 = f(SL_SQ);
+    s.sq4 = reinterpret_cast<float4 *>(s.sq0);
     s.nch = L.nch;
     s.tau0 = f(SL_TAU);
     s.astride = (uint32_t)(L.stride / sizeof(float));

@@ -447,7 +447,8 @@ __global__ __launch_bounds__(256) void propose_kernel(StateView st, int64_t H, c
             st.r[q] = rp;
             st.t[q] = 0u;
             st.nseen[q] = 0u;
-            for (int i = 0; i < NSQ * st.nch; ++i) st.sq0[(size_t)i * st.astride + q] = 0.0f;
+            for (int i = 0; i < NG * st.nch; ++i)
+                st.sq4[(size_t)q * (NG * st.nch) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         atomicAdd(&hist[radius_bin(rp, r1)], 1u);
     }
