@@ -157,6 +157,21 @@ int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, c
 int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
                void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): hk_iterate without a workspace argument. Its scratch is a static
+ * array of HK_STATIC_SCRATCH_BYTES in the library's device code, one copy per GPU the library runs
+ * on, held from the first hk_create on that GPU until the process ends. The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and never profiles. A call whose sets need
+ * more scratch than that (hk_workspace_bytes_batch of the sets: about 80 bytes per stored light
+ * vertex and 24 per hit point, e.g. up to about 800k light vertices in one call) returns
+ * HK_E_SMALL_BUFFER before any work is enqueued; other arguments and errors as hk_iterate. Every
+ * call on one GPU shares that GPU's array (it keeps the last call's contents; nothing in it has to
+ * start at zero): calls that overlap on one GPU, from any context or stream, race and must be
+ * ordered by the caller. */
+#define HK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int hk_iterate_static(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, void *const *state,
+                      hipStream_t stream);
+
 /* Captures the launches of one hk_iterate call (same arguments) into a HIP graph, *out. Nothing runs
  * at capture and no set advances. Each hk_graph_launch then runs one iteration of those sets on
  * `stream` (the iteration index, J and the radius bounds come from the device-resident state). The

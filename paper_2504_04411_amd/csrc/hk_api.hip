@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,9 +60,39 @@ struct ProfEv {
 
 }  // namespace
 
+// Scratch of hk_iterate_static (the entry point for callers that cannot allocate): a fixed array in
+// the library's device code, one copy on every GPU the library runs on, held until the process ends.
+// Host code never uses its name as an address: each device's copy is looked up once with
+// hipGetSymbolAddress (with that device current) and its pointer kept in static_scratch_ptr.
+constexpr size_t STATIC_SCRATCH_BYTES = HK_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `device`'s copy of the scratch array; `device` must be current.
+int static_scratch_ptr(int device, void **out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(HK_E_UNSUPPORTED, "device index %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HK_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return HK_OK;
+}
+}  // namespace
+
 struct hk_ctx {
     hk_params p;
     int device = 0;
+    void *scratch = nullptr;       // this device's copy of the static scratch array
     SetInfo sets[MAX_SETS];
     uint64_t gen = 0;
     bool prof = false;
@@ -159,8 +190,10 @@ extern "C" int hk_create(const hk_params *p, hk_ctx **out)
         delete c;
         return fail(HK_E_HIP, "hipGetDevice failed");
     }
-    // set-up that later calls must not repeat: the second stream and its events
-    rc = ensure_streams(c);
+    // set-up that later calls must not repeat: the static scratch address of this device, the
+    // second stream and its events
+    rc = static_scratch_ptr(c->device, &c->scratch);
+    if (!rc) rc = ensure_streams(c);
     if (rc) {
         (void)hk_destroy(c);
         return rc;
@@ -583,6 +616,26 @@ extern "C" int hk_iterate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     rc = enqueue(ctx, n_sets, set_ids, ph, state, workspace, workspace_bytes, stream, ctx->prof, nullptr, nullptr);
+    if (rc) return rc;
+    for (int s = 0; s < n_sets; ++s) advance(ctx->sets[set_ids[s]], ph[s].J_emitted);
+    return HK_OK;
+}
+
+extern "C" int hk_iterate_static(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph,
+                                 void *const *state, hipStream_t stream)
+{
+    if (!ctx) return fail(HK_E_INVALID_ARG, "hk_iterate_static: NULL context");
+    int rc = validate(ctx, n_sets, set_ids, ph, state, ctx->scratch);
+    if (rc) return rc;
+    for (const auto &b : make_batches(ctx, n_sets, set_ids, ph)) {
+        const size_t need = batch_layout(ctx, b, set_ids, ph).total;
+        if (need > STATIC_SCRATCH_BYTES)
+            return fail(HK_E_SMALL_BUFFER, "hk_iterate_static: the call needs %zu bytes of scratch, the static "
+                        "scratch holds %zu (use hk_iterate with a workspace)", need, STATIC_SCRATCH_BYTES);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    rc = enqueue(ctx, n_sets, set_ids, ph, state, ctx->scratch, STATIC_SCRATCH_BYTES, stream, false, nullptr,
+                 nullptr);
     if (rc) return rc;
     for (int s = 0; s < n_sets; ++s) advance(ctx->sets[set_ids[s]], ph[s].J_emitted);
     return HK_OK;

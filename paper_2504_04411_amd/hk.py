@@ -93,6 +93,8 @@ def lib():
                                 c.c_void_p, c.c_void_p, _vp, _vp, c.c_size_t, _vp], c.c_int),
             "hk_iterate": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp,
                             c.c_size_t, _vp], c.c_int),
+            "hk_iterate_static": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(_vp), _vp],
+                                  c.c_int),
             "hk_read_radiance": ([_vp, c.c_int, _vp, _vp * 3, _vp], c.c_int),
             "hk_read_radii": ([_vp, c.c_int, _vp, _vp, _vp], c.c_int),
             "hk_read_debug": ([_vp, c.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp], c.c_int),
@@ -235,6 +237,17 @@ def hk_iterate(ctx, set_ids, photons, states, workspace, workspace_bytes, stream
     phs = (hk_photons * n)(*photons)
     sts = (_vp * n)(*states)
     check(lib().hk_iterate(ctx, n, ids, phs, sts, workspace, int(workspace_bytes), stream))
+
+
+def hk_iterate_static(ctx, set_ids, photons, states, stream):
+    n = len(set_ids)
+    ids = (ctypes.c_int * n)(*set_ids)
+    phs = (hk_photons * n)(*photons)
+    sts = (_vp * n)(*states)
+    check(lib().hk_iterate_static(ctx, n, ids, phs, sts, stream))
+
+
+HK_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def _set_arrays(set_ids, photons, states):
