@@ -472,7 +472,9 @@ def main():
     ap.add_argument("--tune-at", type=int, default=-1,
                     help="untimed iterations before the autotuner samples the state (default: K / 2, the middle "
                          "of the timed run; at least W)")
-    ap.add_argument("--workers", type=int, default=15, help="batch-generating worker processes (<= 15)")
+    ap.add_argument("--workers", type=int, default=15,
+                    help="batch-generating worker processes (<= 15; 0: generate in this process, as profiled "
+                         "runs do, where every child process would load the profiler too)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the legs, copy a MIB-sized device buffer once (reference for HBM traffic "
                          "counters: it reads and writes exactly MIB MiB)")
@@ -484,7 +486,7 @@ def main():
 
     # the batch generators run in spawned processes, started before anything touches the GPU
     from workloads import generators as G
-    pool = G.spawn_pool(min(max(args.workers, 1), 15))
+    pool = G.spawn_pool(min(args.workers, 15))
 
     import torch
     from paper_2504_04411_amd import hk

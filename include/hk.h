@@ -242,7 +242,7 @@ int hk_graph_create_box(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_bo
                         const uint64_t *seeds, const hk_photons *ph, void *const *state, void *workspace,
                         size_t workspace_bytes, int flags, hk_graph **out);
 
-/* Times one iteration of the given sets for each of 36 settings (cell_scale 0.7 / 1 / 1.4 x
+/* Times one iteration of the given sets for each of 48 settings (cell_scale 0.35 / 0.5 / 0.7 / 1 x
  * lanes_light 4 / 8 / 16 x heavy_cost 1024 / 2048 / 4096 / 16384; the fastest of three runs of each)
  * and keeps the fastest setting in the context
  * (copied to *chosen when non-NULL). Each trial runs on scratch[s] (device, hk_state_bytes of the

@@ -100,6 +100,8 @@ struct hk_ctx {
     hipStream_t cap = nullptr;     // stream used for graph capture (created on first use)
     hipStream_t aux = nullptr;     // second stream: critical values run beside the grid builds
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t gs[GRID_STREAMS] = {};    // streams 1.. of the grid builds (stream 0 is the caller's)
+    hipEvent_t gfork = nullptr, gjoin[GRID_STREAMS] = {};
 };
 
 struct hk_graph {
@@ -212,6 +214,11 @@ extern "C" int hk_destroy(hk_ctx *ctx)
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->join) (void)hipEventDestroy(ctx->join);
+    for (int g = 0; g < GRID_STREAMS; ++g) {
+        if (ctx->gs[g]) (void)hipStreamDestroy(ctx->gs[g]);
+        if (ctx->gjoin[g]) (void)hipEventDestroy(ctx->gjoin[g]);
+    }
+    if (ctx->gfork) (void)hipEventDestroy(ctx->gfork);
     delete ctx;
     return HK_OK;
 }
@@ -312,12 +319,12 @@ extern "C" int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, dou
     g.max_iters = ctx->p.max_iters;
     g.r1 = (float)r1;
     g.vcm = vcm;
-    g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
-    g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
-    g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
-    g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
-    g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
-    g.part = reinterpret_cast<uint32_t *>(w + W.part);
+    g.keyA = reinterpret_cast<uint32_t *>(w + W.sort[0].keyA);
+    g.keyB = reinterpret_cast<uint32_t *>(w + W.sort[0].keyB);
+    g.valA = reinterpret_cast<uint32_t *>(w + W.sort[0].valA);
+    g.valB = reinterpret_cast<uint32_t *>(w + W.sort[0].valB);
+    g.hist = reinterpret_cast<uint32_t *>(w + W.sort[0].hist);
+    g.part = reinterpret_cast<uint32_t *>(w + W.sort[0].part);
     // lower bounds lb_i = r_min sqrt(i^(alpha - 1)) of Eq. radiusupdate, float64 then one rounding;
     // they decrease with i, so a radius at or above lb_1 = r_min never grows on a shrink
     std::vector<float> lb((size_t)ctx->p.max_iters + 2);
@@ -454,6 +461,11 @@ static int ensure_streams(hk_ctx *ctx)
     if (!ctx->aux) HIP_TRY(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
     if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
     if (!ctx->join) HIP_TRY(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+    if (!ctx->gfork) HIP_TRY(hipEventCreateWithFlags(&ctx->gfork, hipEventDisableTiming));
+    for (int g = 1; g < GRID_STREAMS; ++g) {
+        if (!ctx->gs[g]) HIP_TRY(hipStreamCreateWithFlags(&ctx->gs[g], hipStreamNonBlocking));
+        if (!ctx->gjoin[g]) HIP_TRY(hipEventCreateWithFlags(&ctx->gjoin[g], hipEventDisableTiming));
+    }
     return HK_OK;
 }
 
@@ -505,7 +517,13 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(ctx->join, ctx->aux));
-        // 3. per set: sort the photons into the grid
+        // 3. per set: sort the photons into the grid; the sets' builds are independent and run on
+        //    W.ngs streams at once (set k on stream k mod ngs, stream 0 the caller's), joined before
+        //    the work list
+        if (W.ngs > 1) {
+            HIP_TRY(hipEventRecord(ctx->gfork, stream));
+            for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(ctx->gs[gi], ctx->gfork, 0));
+        }
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
@@ -520,19 +538,25 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
                 g.src.mis[a] = vcm ? P.mis[a] : nullptr;
             }
             g.n = P.n_stored;
-            g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
-            g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
-            g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
-            g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
-            g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
-            g.part = reinterpret_cast<uint32_t *>(w + W.part);
-            g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
+            const int gs = k % W.ngs;                 // grid stream of this set
+            const SortScratch &SS = W.sort[gs];
+            g.keyA = reinterpret_cast<uint32_t *>(w + SS.keyA);
+            g.keyB = reinterpret_cast<uint32_t *>(w + SS.keyB);
+            g.valA = reinterpret_cast<uint32_t *>(w + SS.valA);
+            g.valB = reinterpret_cast<uint32_t *>(w + SS.valB);
+            g.hist = reinterpret_cast<uint32_t *>(w + SS.hist);
+            g.part = reinterpret_cast<uint32_t *>(w + SS.part);
+            g.part3 = reinterpret_cast<uint32_t *>(w + SS.part3);
             g.cstart = ws_cstart + W.cell_base[k];
             g.pay = ws_pay + W.pay_off[k];
             g.pstride = W.pstride;
             g.pay_off = W.pay_off[k];
             g.ncells_bound = W.max_cells[k];
-            build_grid(g, stream);
+            build_grid(g, gs == 0 ? stream : ctx->gs[gs]);
+        }
+        for (int gi = 1; gi < W.ngs; ++gi) {
+            HIP_TRY(hipEventRecord(ctx->gjoin[gi], ctx->gs[gi]));
+            HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin[gi], 0));
         }
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
         HIP_TRY(hipStreamWaitEvent(stream, ctx->join, 0));
@@ -886,9 +910,9 @@ extern "C" int hk_autotune(hk_ctx *ctx, int n_sets, const int *set_ids, const hk
         if (!scratch[s] || !aligned(scratch[s]) || scratch[s] == state[s])
             return fail(HK_E_INVALID_ARG, "scratch of set %d must be a separate 256-byte aligned buffer", set_ids[s]);
     HIP_TRY(hipSetDevice(ctx->device));
-    static const float cells[] = {0.7f, 1.0f, 1.4f};
+    static const float cells[] = {0.35f, 0.5f, 0.7f, 1.0f};
     constexpr int TUNE_REPS = 3;
-    constexpr int n_trials = 3 * 3 * 4;
+    constexpr int n_trials = 4 * 3 * 4;
     static const int lanes[] = {4, 8, 16};
     static const int heavies[] = {1024, 2048, 4096, 16384};
     const hk_params saved = ctx->p;
@@ -1084,13 +1108,13 @@ extern "C" int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_ph
         g.src.mis[a] = nullptr;
     }
     g.n = P.n_stored;
-    g.keyA = reinterpret_cast<uint32_t *>(w + W.keyA);
-    g.keyB = reinterpret_cast<uint32_t *>(w + W.keyB);
-    g.valA = reinterpret_cast<uint32_t *>(w + W.valA);
-    g.valB = reinterpret_cast<uint32_t *>(w + W.valB);
-    g.hist = reinterpret_cast<uint32_t *>(w + W.hist);
-    g.part = reinterpret_cast<uint32_t *>(w + W.part);
-    g.part3 = reinterpret_cast<uint32_t *>(w + W.part3);
+    g.keyA = reinterpret_cast<uint32_t *>(w + W.sort[0].keyA);
+    g.keyB = reinterpret_cast<uint32_t *>(w + W.sort[0].keyB);
+    g.valA = reinterpret_cast<uint32_t *>(w + W.sort[0].valA);
+    g.valB = reinterpret_cast<uint32_t *>(w + W.sort[0].valB);
+    g.hist = reinterpret_cast<uint32_t *>(w + W.sort[0].hist);
+    g.part = reinterpret_cast<uint32_t *>(w + W.sort[0].part);
+    g.part3 = reinterpret_cast<uint32_t *>(w + W.sort[0].part3);
     g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
     g.pay = reinterpret_cast<float4 *>(w + W.pay);
     g.pstride = W.pstride;

@@ -135,64 +135,104 @@ void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const ui
 // LSD radix sort of (key, value) pairs
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *keys, int64_t n, int shift,
-                                                             uint32_t *hist, int nblk)
+// Every wavefront of a radix block owns a chunk of RS_CHUNK consecutive keys (RS_ITEMS rounds of 64):
+// segment seg = block * RS_WAVES + wave. Histograms, offsets and the scatter are per segment, so the
+// scatter's waves never wait for each other.
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_CHUNK = 64 * RS_ITEMS;
+static_assert(RS_TILE == RS_WAVES * RS_CHUNK, "a radix block is its waves' chunks");
+
+// Digit counts of every segment of the block: hist[d * nseg + seg]. The chunk's keys are loaded
+// together (RS_ITEMS loads in flight per lane), then counted in the wave's own LDS histogram.
+__device__ __forceinline__ void rs_count_store(uint32_t (&cnt)[RS_WAVES][256], uint32_t *hist, int nseg)
 {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        const int64_t k = base + (int64_t)i * RS_THREADS + threadIdx.x;
-        if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 255u], 1u);
+    const int seg0 = blockIdx.x * RS_WAVES;
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) {
+        const int w = i & (RS_WAVES - 1), d = i / RS_WAVES;
+        if (seg0 + w < nseg) hist[(int64_t)d * nseg + seg0 + w] = cnt[w][d];
     }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// One block per digit d: the blocks' counts of d become their exclusive prefix over the blocks (in
-// place), and the digit's total goes to dtot[d].
-__global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nblk, uint32_t *dtot)
+__global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *keys, int64_t n, int shift,
+                                                             uint32_t *hist, int nseg)
 {
-    uint32_t *h = hist + (int64_t)blockIdx.x * nblk;
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t base = ((int64_t)blockIdx.x * RS_WAVES + w) * RS_CHUNK + lane;
+    uint32_t k[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) k[i] = base + 64 * i < n ? keys[base + 64 * i] : 0u;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i)
+        if (base + 64 * i < n) atomicAdd(&cnt[w][(k[i] >> shift) & 255u], 1u);
+    rs_count_store(cnt, hist, nseg);
+}
+
+// One block per digit d: the segments' counts of d become their exclusive prefix over the segments
+// (in place), and the digit's total goes to dtot[d].
+__global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nseg, uint32_t *dtot)
+{
+    uint32_t *h = hist + (int64_t)blockIdx.x * nseg;
     uint32_t carry = 0;
-    for (int base = 0; base < nblk; base += 256) {
+    for (int base = 0; base < nseg; base += 256) {
         const int k = base + threadIdx.x;
-        const uint32_t v = k < nblk ? h[k] : 0u;
+        const uint32_t v = k < nseg ? h[k] : 0u;
         uint32_t tot;
         const uint32_t ex = block_excl_scan(v, &tot);
-        if (k < nblk) h[k] = carry + ex;
+        if (k < nseg) h[k] = carry + ex;
         carry += tot;
     }
     if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// Stable scatter: a block's first position for digit d is the exclusive scan of the digit totals at
-// d plus the block's prefix within d. Items are visited in rounds of 256 consecutive keys; inside a
-// round the rank of a key among equal digits is (count in earlier rounds) + (count in lower waves)
-// + (lower lanes of the same wave, from eight ballots).
+// Stable scatter, one wavefront per segment and no barrier between the block's waves. The wave's
+// first position for digit d is the exclusive scan of the digit totals at d plus the segment's
+// prefix within d, kept in the wave's own LDS row; the chunk is visited in rounds of 64 consecutive
+// keys, a key's rank among the round's equal digits comes from eight ballots, and the first lane of
+// each digit then advances the row by the digit's count in the round (a wave's LDS accesses are
+// performed in order, so the next round reads the advanced value).
 // With `inv` (the last pass), the inverse permutation is written instead of the sorted values:
 // inv[source index] = sorted position.
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                 uint32_t *kout, uint32_t *vout, int64_t n,
-                                                                int shift, const uint32_t *offs, int nblk,
+                                                                int shift, const uint32_t *offs, int nseg,
                                                                 const uint32_t *dtot, uint32_t *inv)
 {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[4][256];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t all;
-    const uint32_t dbase = block_excl_scan(dtot[tid], &all);
-    run[tid] = dbase + offs[(int64_t)tid * nblk + blockIdx.x];
-    for (int i = 0; i < 4; ++i) wcnt[i][tid] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    __shared__ uint32_t row[RS_WAVES][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int seg = blockIdx.x * RS_WAVES + w;
+    if (seg >= nseg) return;
+    // digit bases: four digits per lane, an exclusive scan over the lanes
+    uint32_t t[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        t[j] = dtot[4 * lane + j];
+        sum += t[j];
+    }
+    uint32_t ex = wave_incl_scan(sum) - sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int d = 4 * lane + j;
+        row[w][d] = ex + offs[(int64_t)d * nseg + seg];
+        ex += t[j];
+    }
+    const int64_t base = (int64_t)seg * RS_CHUNK + lane;
+    uint32_t k[RS_ITEMS], v[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t q = base + 64 * i;
+        k[i] = q < n ? kin[q] : 0u;
+        v[i] = vin ? (q < n ? vin[q] : 0u) : (uint32_t)q;
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const int64_t k = base + (int64_t)it * RS_THREADS + tid;
-        const bool valid = k < n;
-        const uint32_t key = valid ? kin[k] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const bool valid = base + 64 * i < n;
+        const uint32_t d = (k[i] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -201,22 +241,17 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
+        const uint32_t pos = row[w][d] + rank;
+        __builtin_amdgcn_wave_barrier();
         if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int i = 0; i < w; ++i) pos += wcnt[i][d];
-            kout[pos] = key;
-            const uint32_t src = vin ? vin[k] : (uint32_t)k;
+            kout[pos] = k[i];
             if (inv)
-                inv[src] = pos;
+                inv[v[i]] = pos;
             else
-                vout[pos] = src;
+                vout[pos] = v[i];
+            if (rank == 0) row[w][d] = pos + (uint32_t)__popcll(peers);
         }
-        __syncthreads();
-        run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-        wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -225,16 +260,17 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
 // (sorted position -> source index), or with `inverse` the inverse permutation (source index ->
 // sorted position), which the last pass then writes instead.
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
-                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse)
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse, bool first_hist_done)
 {
     const int nblk = (int)cdiv(n, RS_TILE);
+    const int nseg = (int)cdiv(n, RS_CHUNK);
     uint32_t *ki = kA, *vi = nullptr, *ko = kB, *vo = vB;
     uint32_t *vspare = vA;
     for (int shift = 0; shift < bits; shift += 8) {
         const bool last = shift + 8 >= bits;
-        rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nblk);
-        rs_offsets_kernel<<<256, 256, 0, s>>>(hist, nblk, part);
-        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblk, part,
+        if (shift > 0 || !first_hist_done) rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nseg);
+        rs_offsets_kernel<<<256, 256, 0, s>>>(hist, nseg, part);
+        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nseg, part,
                                                       (last && inverse) ? vo : nullptr);
         uint32_t *kt = ki;
         ki = ko;
@@ -351,24 +387,69 @@ void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream
     plan_fixed_kernel<<<1, 64, 0, s>>>(hdr, cell, max_cells);
 }
 
-__device__ __forceinline__ uint32_t cell_key(const SetHeader *hdr, float x, float y, float z)
+// The plan's grid: domain corner, cells per unit length and cell counts per axis.
+struct GridPlan {
+    float lo[3], inv[3];
+    int dims[3];
+};
+
+__device__ __forceinline__ GridPlan grid_plan(const SetHeader *hdr)
+{
+    GridPlan g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = hdr->dom_lo[a];
+        g.inv[a] = hdr->cell_inv[a];
+        g.dims[a] = hdr->dims[a];
+    }
+    return g;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const GridPlan &g, float x, float y, float z)
 {
     const float p[3] = {x, y, z};
     uint32_t c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float f = floorf((p[a] - hdr->dom_lo[a]) * hdr->cell_inv[a]);
-        if (!(f >= 0.0f && f < (float)hdr->dims[a])) return KEY_OUTSIDE;
+        const float f = floorf((p[a] - g.lo[a]) * g.inv[a]);
+        if (!(f >= 0.0f && f < (float)g.dims[a])) return KEY_OUTSIDE;
         c[a] = (uint32_t)f;
     }
-    return (c[2] * (uint32_t)hdr->dims[1] + c[1]) * (uint32_t)hdr->dims[0] + c[0];
+    return (c[2] * (uint32_t)g.dims[1] + c[1]) * (uint32_t)g.dims[0] + c[0];
 }
 
-__global__ __launch_bounds__(256) void keys_kernel(const SetHeader *hdr, const float *px, const float *py,
-                                                   const float *pz, int64_t n, uint32_t *keys)
+// Cell keys of a radix block's photons together with their segments' histograms of the low 8 bits
+// (the first sort pass's histogram, laid out as rs_hist_kernel writes it). A lane loads the positions
+// of its RS_ITEMS keys together.
+__global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *hdr, const float *px,
+                                                               const float *py, const float *pz, int64_t n,
+                                                               uint32_t *keys, uint32_t *hist, int nseg)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q < n) keys[q] = cell_key(hdr, px[q], py[q], pz[q]);
+    __shared__ uint32_t cnt[RS_WAVES][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0u;
+    const GridPlan gp = grid_plan(hdr);
+    __syncthreads();
+    const int64_t base = ((int64_t)blockIdx.x * RS_WAVES + w) * RS_CHUNK + lane;
+    float x[RS_ITEMS], y[RS_ITEMS], z[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t q = base + 64 * i;
+        const bool in = q < n;
+        x[i] = in ? px[q] : 0.0f;
+        y[i] = in ? py[q] : 0.0f;
+        z[i] = in ? pz[q] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t q = base + 64 * i;
+        if (q < n) {
+            const uint32_t key = cell_key(gp, x[i], y[i], z[i]);
+            keys[q] = key;
+            atomicAdd(&cnt[w][key & 255u], 1u);
+        }
+    }
+    rs_count_store(cnt, hist, nseg);
 }
 
 // inv[original index] = sorted position
@@ -384,9 +465,11 @@ __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, 
     const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
     pay[q] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
     float4 *bc = pairs + 2 * (int64_t)q;
+    // the (normal, dVM) entry is read only by a normal test or by vertex merging: without either it
+    // is not written (a third of the scattered stores)
     if (src.nrm[0])
         bc[0] = make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm);
-    else
+    else if (src.mis[0])
         bc[0] = make_float4(0.0f, 0.0f, 1.0f, dvm);
     bc[1] = make_float4(R, G, B, dvcm);
 }
@@ -438,9 +521,11 @@ void build_grid(const GridLaunch &g, hipStream_t s)
     zero_kernel<<<(int)cdiv(nc, 256 * ZERO_PER), 256, 0, s>>>(g.cstart, nc, &g.hdr->ncells, 1);
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
-        keys_kernel<<<nb, 256, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
+        const int nblk = (int)cdiv(n, RS_TILE);
+        keys_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA,
+                                                      g.hist, (int)cdiv(n, RS_CHUNK));
         uint32_t *ks, *inv;
-        radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true);
+        radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true, true);
         // the set's pairs: plane base + pstride + 2 pay_off, with plane base = g.pay - pay_off
         permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pay + g.pstride + g.pay_off);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
@@ -610,7 +695,7 @@ void init_set(const InitLaunch &g, hipStream_t s)
     const int nb = (int)cdiv(n, 256);
     morton_kernel<<<nb, 256, 0, s>>>(g.st.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA);
     uint32_t *ks, *vs;
-    radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs, false);
+    radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 30, g.hist, g.part, s, &ks, &vs, false, false);
     init_state_kernel<<<nb, 256, 0, s>>>(g.src, g.st, vs, n, g.r1);
 }
 

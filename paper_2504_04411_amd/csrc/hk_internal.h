@@ -173,12 +173,21 @@ inline uint32_t max_cells_for(int64_t n_photons)
     return (uint32_t)mc;
 }
 
+// The grids of a batch's sets are built on up to GRID_STREAMS streams at once (the sets are
+// independent until the gather); each stream has its own sort scratch.
+constexpr int GRID_STREAMS = 4;
+
+struct SortScratch {
+    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
+};
+
 // Workspace of one batched iteration (or of the kernel ordering in hk_set_kernels).
 struct WsLayout {
     int n_sets = 0;
+    int ngs = 1;              // grid streams of the batch: min(sets, GRID_STREAMS)
     int64_t n_total = 0, h_total = 0, n_max = 0;
     int64_t pstride = 0;      // payload plane entries: the batch's photons, then one point at infinity
-    size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
+    SortScratch sort[GRID_STREAMS];
     size_t cstart = 0, pay = 0;
     size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, lcost = 0, counts = 0, desc = 0;
     uint32_t pay_off[MAX_BATCH] = {}, cell_base[MAX_BATCH] = {}, max_cells[MAX_BATCH] = {};
@@ -209,15 +218,19 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     W.n_max = nmax;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    W.keyA = take(4 * (size_t)nmax);
-    W.keyB = take(4 * (size_t)nmax);
-    W.valA = take(4 * (size_t)nmax);
-    W.valB = take(4 * (size_t)nmax);
-    const int64_t nblk = cdiv(nmax, RS_TILE);
-    W.hist = take(4 * (size_t)(256 * nblk));
-    const int64_t nscan = cdiv(256 * nblk, SCAN_TILE) + 1;
-    W.part = take(4 * (size_t)(nscan > 256 ? nscan : 256));   // scan partials, or the 256 digit totals
-    W.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
+    W.ngs = n_sets < GRID_STREAMS ? (n_sets > 0 ? n_sets : 1) : GRID_STREAMS;
+    for (int g = 0; g < W.ngs; ++g) {
+        SortScratch &S = W.sort[g];
+        S.keyA = take(4 * (size_t)nmax);
+        S.keyB = take(4 * (size_t)nmax);
+        S.valA = take(4 * (size_t)nmax);
+        S.valB = take(4 * (size_t)nmax);
+        const int64_t nblk = cdiv(nmax, RS_TILE);
+        S.hist = take(4 * (size_t)(256 * (RS_TILE / 64) * nblk));      // per digit and wavefront chunk
+        const int64_t nscan = cdiv(256 * nblk, SCAN_TILE) + 1;
+        S.part = take(4 * (size_t)(nscan > 256 ? nscan : 256));   // scan partials, or the 256 digit totals
+        S.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
+    }
     W.cstart = take(4 * (size_t)(cells + 1));
     W.pstride = W.n_total + 1;
     W.pay = take(16 * (size_t)W.pstride * PAY_VEC + 256);

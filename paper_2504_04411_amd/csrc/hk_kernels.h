@@ -134,8 +134,9 @@ void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, con
                      bool nrm_test, float cos_min, float it_code, uint16_t *feat, uint32_t *counts, hipStream_t s);
 void launch_propose(const StateView &st, int64_t H, const float *y, float margin, hipStream_t s);
 
+// first_hist_done: the first pass's histogram is already in `hist` (written with the keys).
 void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t n, int bits, uint32_t *hist,
-                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse);
+                uint32_t *part, hipStream_t s, uint32_t **kres, uint32_t **vres, bool inverse, bool first_hist_done);
 void build_grid(const GridLaunch &g, hipStream_t s);
 void init_set(const InitLaunch &g, hipStream_t s);
 void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const uint32_t *dlen = nullptr,

@@ -189,14 +189,15 @@ def test_autotune_keeps_state_and_picks_a_candidate():
     torch.cuda.synchronize()
     print(f"  chosen: {t}", flush=True)
     assert torch.equal(before, est.states[0])
-    assert t["cell_scale"] in [np.float32(c) for c in (0.7, 1.0, 1.4)]
+    assert t["cell_scale"] in [np.float32(c) for c in (0.35, 0.5, 0.7, 1.0)]
     assert t["lanes_light"] in (4, 8, 16) and t["heavy_cost"] in (1024, 2048, 4096, 16384)
     assert est.tuning() == t
     assert est.stats(0)["iterations"] == 1
 
 
 @pytest.mark.parametrize("tuning", [dict(cell_scale=0.7, heavy_cost=1024, lanes_light=4, lanes_heavy=16),
-                                    dict(cell_scale=1.4, heavy_cost=16384, lanes_light=16, lanes_heavy=64)])
+                                    dict(cell_scale=1.4, heavy_cost=16384, lanes_light=16, lanes_heavy=64),
+                                    dict(cell_scale=0.35, heavy_cost=2048, lanes_light=8, lanes_heavy=64)])
 def test_other_tunings_meet_oracle_parity(tuning):
     G, GP, DP = _mods()
     w = G.box_scene(seed=1, res=40, J=200_000, n_iter=6)

@@ -440,11 +440,24 @@ def batch(spec) -> PhotonBatch:
     raise ValueError(f"unknown batch kind {kind!r}")
 
 
+class InProcess:
+    """The executor interface of ``spawn_pool`` run in the calling process (no worker processes)."""
+
+    def map(self, fn, items):
+        return map(fn, items)
+
+    def shutdown(self):
+        pass
+
+
 def spawn_pool(workers: int):
     """Worker processes for ``batch``, started with the spawn method: fresh interpreters that share
-    nothing with a parent that may already hold a GPU (no fork of such a process)."""
+    nothing with a parent that may already hold a GPU (no fork of such a process). With workers <= 0
+    the batches are generated in the calling process instead."""
+    if workers <= 0:
+        return InProcess()
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
-    ex = ProcessPoolExecutor(max_workers=max(1, workers), mp_context=multiprocessing.get_context("spawn"))
-    list(ex.map(int, range(max(1, workers))))          # start the workers now
+    ex = ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn"))
+    list(ex.map(int, range(workers)))          # start the workers now
     return ex
