@@ -40,7 +40,7 @@ int fail(int code, const char *fmt, ...)
 constexpr int MAX_SETS = 256;
 constexpr int64_t MAX_KERNELS = ((int64_t)1 << Q_BITS) - 1;       // per set
 constexpr int64_t MAX_STORED = ((int64_t)1 << 27) - 1;            // per set and iteration
-constexpr int64_t MAX_BATCH_PHOTONS = ((int64_t)1 << 27) - 1;     // per gather launch (32-bit offsets)
+// per gather launch: max_batch_photons(rec), the records' byte offsets fit 32 bits
 
 struct SetInfo {
     bool init = false;
@@ -393,8 +393,11 @@ static int validate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photon
         if (P.J_emitted < 1 || P.n_stored < 0 || (uint64_t)P.n_stored > P.J_emitted)
             return fail(HK_E_INVALID_ARG, "set %d: need 1 <= J_emitted and 0 <= n_stored <= J_emitted", id);
         if (P.J_emitted > (uint64_t)1 << 52) return fail(HK_E_INVALID_ARG, "J_emitted too large");
-        if (P.n_stored > MAX_STORED)
-            return fail(HK_E_UNSUPPORTED, "set %d: at most 2^27 - 1 stored light vertices per set", id);
+        const int64_t lim = max_batch_photons(pay_rec(nrm_test_of(ctx, id, P) || vcm));
+        if (P.n_stored > MAX_STORED || P.n_stored > lim)
+            return fail(HK_E_UNSUPPORTED, "set %d: at most %lld stored light vertices per set (%s)", id,
+                        (long long)(lim < MAX_STORED ? lim : MAX_STORED),
+                        lim < MAX_STORED ? "48-byte records with the normal test or merging" : "2^27 - 1");
         if (P.n_stored > 0) {
             for (int a = 0; a < 3; ++a)
                 if (!P.pos[a] || !P.flux[a]) return fail(HK_E_INVALID_ARG, "set %d: pos/flux is NULL", id);
@@ -409,7 +412,7 @@ static int validate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photon
 }
 
 // Batches of one gather launch: sets of equal normal-test flag, at most MAX_BATCH sets and
-// MAX_BATCH_PHOTONS stored light vertices each, in call order within a flag.
+// max_batch_photons stored light vertices each, in call order within a flag.
 static std::vector<std::vector<int>> make_batches(const hk_ctx *ctx, int n_sets, const int *set_ids,
                                                   const hk_photons *ph)
 {
@@ -417,9 +420,10 @@ static std::vector<std::vector<int>> make_batches(const hk_ctx *ctx, int n_sets,
     for (int flag = 1; flag >= 0; --flag) {
         std::vector<int> cur;
         int64_t np = 0;
+        const int64_t lim = max_batch_photons(pay_rec(flag || ctx->p.mode == HK_MODE_VCM));
         for (int s = 0; s < n_sets; ++s) {
             if ((int)nrm_test_of(ctx, set_ids[s], ph[s]) != flag) continue;
-            if (!cur.empty() && ((int)cur.size() == MAX_BATCH || np + ph[s].n_stored > MAX_BATCH_PHOTONS)) {
+            if (!cur.empty() && ((int)cur.size() == MAX_BATCH || np + ph[s].n_stored > lim)) {
                 out.push_back(cur);
                 cur.clear();
                 np = 0;
@@ -490,6 +494,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         const WsLayout W = batch_layout(ctx, b, set_ids, ph);
         const int nb = (int)b.size();
         const bool nrm_test = nrm_test_of(ctx, set_ids[b[0]], ph[b[0]]);
+        const int rec = pay_rec(nrm_test || vcm);          // float4s per payload record
         ProfEv *pe = prof ? prof_slot(ctx) : nullptr;
         if (prof && !pe) return fail(HK_E_HIP, "hipEventCreate failed");
         if (pe) HIP_TRY(hipEventRecord(pe->e[0], stream));
@@ -548,8 +553,8 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             g.part = reinterpret_cast<uint32_t *>(w + SS.part);
             g.part3 = reinterpret_cast<uint32_t *>(w + SS.part3);
             g.cstart = ws_cstart + W.cell_base[k];
-            g.pay = ws_pay + W.pay_off[k];
-            g.pstride = W.pstride;
+            g.pay = ws_pay;
+            g.rec = rec;
             g.pay_off = W.pay_off[k];
             g.ncells_bound = W.max_cells[k];
             build_grid(g, gs == 0 ? stream : ctx->gs[gs]);
@@ -607,7 +612,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
         uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
         launch_split(flag, ids, W.h_total, (uint32_t)p.heavy_cost, tiles, heavy, light,
-                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, ws_pay + W.n_total, stream);
+                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, ws_pay + W.n_total * rec, stream);
         SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
         launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
         BatchArgs a{};
@@ -1117,11 +1122,11 @@ extern "C" int hk_mlp_features(hk_ctx *ctx, int set_id, void *state, const hk_ph
     g.part3 = reinterpret_cast<uint32_t *>(w + W.sort[0].part3);
     g.cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
     g.pay = reinterpret_cast<float4 *>(w + W.pay);
-    g.pstride = W.pstride;
+    g.rec = pay_rec(nrm_test || ctx->p.mode == HK_MODE_VCM);
     g.pay_off = 0;
     g.ncells_bound = W.max_cells[0];
     build_grid(g, stream);
-    launch_features(st, S.H, g.cstart, g.pay, g.pstride, nrm_test, ctx->p.normal_cos_min, it_code, feat, counts,
+    launch_features(st, S.H, g.cstart, g.pay, g.rec, nrm_test, ctx->p.normal_cos_min, it_code, feat, counts,
                     stream);
     HIP_TRY(hipGetLastError());
     return HK_OK;

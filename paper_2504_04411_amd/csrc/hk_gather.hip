@@ -123,16 +123,16 @@ struct Cand {
     float4 a, b, f;
 };
 
-// A candidate is addressed by the byte offset of its plane-A entry; its (B, C) pair lies at twice that
-// offset from the pair plane's base.
+// A candidate is addressed by the byte offset of its payload record: (position, luminance), then
+// (flux, dVCM), then (normal, dVM) when the record has it (REC = 3).
 template <bool NRM, bool VCM>
-__device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rA, const float4 *rBC)
+__device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rec)
 {
     Cand P;
-    P.a = ldb(rA, off);
-    P.f = ldb(rBC, 2u * off + 16u);
+    P.a = ldb(rec, off);
+    P.f = ldb(rec, off + 16u);
     P.b = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
-    if (NRM || VCM) P.b = ldb(rBC, 2u * off);
+    if (NRM || VCM) P.b = ldb(rec, off + 32u);
     return P;
 }
 
@@ -214,9 +214,9 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const double *mprefix = reinterpret_cast<const double *>(D.state + D.mprefix);
     const double *fctab = reinterpret_cast<const double *>(D.state + D.fctab);
     const float *lbtab = reinterpret_cast<const float *>(D.state + D.lbtab);
-    // payload planes at a wave-uniform base; photon indices are global (set offset added per row)
-    // payload: the (position, luminance) plane, then (normal, dVM), (flux, dVCM) pairs per photon
-    const float4 *rA = A.pay, *rBC = A.pay + A.pstride;
+    // payload records at a wave-uniform base; photon indices are global (set offset added per row)
+    constexpr uint32_t RB = 16u * pay_rec(NRM || VCM);     // bytes per record
+    const float4 *rec = A.pay;
     const uint32_t *cstart = A.cstart + D.cell_base;
     const int iter = active ? hdr->iter : 1;
     const float Jf = active ? hdr->Jf : 1.0f;
@@ -267,7 +267,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     const float wy = 1.0f / hdr->cell_inv[1], wz = 1.0f / hdr->cell_inv[2];
     const int nbatch = wave_max_i((nrows + G - 1) / G);
 
-    const uint32_t sent = (A.pstride - 1u) << 4;   // byte offset of the point at infinity
+    const uint32_t sent = (A.pstride - 1u) * RB;   // byte offset of the point at infinity
     for (int b = 0; b < nbatch; ++b) {
         const int row = b * G + j;
         uint32_t st = 0, len = 0;
@@ -282,12 +282,12 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         }
         const uint32_t total = group_sum_u<G>(len);
         __syncthreads();
-        L.dl[lane] = st << 4;                     // row start and end, byte offsets into plane A
-        L.re[lane] = (st + len) << 4;
+        L.dl[lane] = st * RB;                     // row start and end, byte offsets of records
+        L.re[lane] = (st + len) * RB;
         __syncthreads();
         const int nsteps = wave_max_i((int)((total + G - 1) / G));
         ncand += total;
-        // Per-lane cursor over the concatenated rows, as a byte offset into plane A: lane j takes the
+        // Per-lane cursor over the concatenated rows, as a byte offset of a record: lane j takes the
         // photons at positions j, j + G, ... of the concatenation. Passing a row's end carries the
         // overshoot into the next row; past the last non-empty row the cursor rests on the point at
         // infinity. The payloads of U steps are loaded together (U candidates in flight per lane),
@@ -296,8 +296,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         const int last = nonempty ? (63 - __clzll((long long)nonempty)) - base : -1;
         int cur = 0;
         uint32_t end = L.re[base];
-        uint32_t off = L.dl[base] + ((uint32_t)j << 4);
-        uint32_t stride = (uint32_t)G << 4;
+        uint32_t off = L.dl[base] + (uint32_t)j * RB;
+        uint32_t stride = (uint32_t)G * RB;
         for (int s0 = 0; s0 < nsteps; s0 += UNROLL_D) {
             Cand P[UNROLL_D];
 #pragma unroll
@@ -312,7 +312,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
                         end = L.re[base + cur];
                     }
                 }
-                P[u] = load_cand<NRM, VCM>(off, rA, rBC);
+                P[u] = load_cand<NRM, VCM>(off, rec);
                 off += stride;
             }
 #pragma unroll

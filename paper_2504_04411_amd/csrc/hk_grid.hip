@@ -6,9 +6,8 @@
 //   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
 //             per-digit prefix over the blocks and digit totals, and a wave-ballot stable scatter
 //   permute   the last sort pass writes the inverse permutation; a coalesced read / scattered write
-//             of the photon payload into sorted order: a plane of (position, luminance) float4s for
-//             the candidate tests, then one 32-byte record per photon of (normal, dVM) and (flux,
-//             dVCM), which the accumulation reads together
+//             of the photon payload into sorted order, one contiguous record per photon:
+//             (position, luminance), (flux, dVCM) and, when read, (normal, dVM)
 //   cstart    photons per cell (wave-aggregated atomics on the sorted keys), exclusive scan:
 //             cstart[c] = first sorted position with key >= c, for c in [0, ncells]
 #include <math.h>
@@ -453,25 +452,25 @@ __global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *
 }
 
 // inv[original index] = sorted position
-// Reads the input photons in their own order (coalesced) and writes each to its sorted position.
-__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *pay,
-                                                      float4 *pairs)
+// Reads the input photons in their own order (coalesced) and writes each one's record, `rec` float4s,
+// at its sorted position: one contiguous 32- or 48-byte store region per photon.
+__global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *recs,
+                                                      int rec)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const uint32_t q = inv[j];
     const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
     const float dvcm = src.mis[0] ? src.mis[0][j] : 0.0f;
-    const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
-    pay[q] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
-    float4 *bc = pairs + 2 * (int64_t)q;
-    // the (normal, dVM) entry is read only by a normal test or by vertex merging: without either it
-    // is not written (a third of the scattered stores)
-    if (src.nrm[0])
-        bc[0] = make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm);
-    else if (src.mis[0])
-        bc[0] = make_float4(0.0f, 0.0f, 1.0f, dvm);
-    bc[1] = make_float4(R, G, B, dvcm);
+    float4 *r = recs + (int64_t)q * rec;
+    r[0] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
+    r[1] = make_float4(R, G, B, dvcm);
+    // the (normal, dVM) entry exists only where a normal test or vertex merging reads it
+    if (rec == 3) {
+        const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
+        r[2] = src.nrm[0] ? make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm)
+                          : make_float4(0.0f, 0.0f, 1.0f, dvm);
+    }
 }
 
 // Four counters per thread: one 16-byte store when all four are live and the array is 16-byte
@@ -526,8 +525,7 @@ void build_grid(const GridLaunch &g, hipStream_t s)
                                                       g.hist, (int)cdiv(n, RS_CHUNK));
         uint32_t *ks, *inv;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true, true);
-        // the set's pairs: plane base + pstride + 2 pay_off, with plane base = g.pay - pay_off
-        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay, g.pay + g.pstride + g.pay_off);
+        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay + g.pay_off * g.rec, g.rec);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
     excl_scan(g.cstart, nc, g.part3, s, &g.hdr->ncells, 1);

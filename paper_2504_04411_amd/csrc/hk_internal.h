@@ -162,9 +162,13 @@ constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;     // keys per radix block
 constexpr int SCAN_TILE = 4096;                    // counters per scan block
 constexpr int SPLIT_TILE = 4096;                   // work-list entries per partition block
-// sorted payload, three float4 per photon: a plane of (x, y, z, luminance), then per photon the pair
-// (nx, ny, nz, dVM), (R, G, B, dVCM)
+// sorted payload: one record of float4s per photon, (x, y, z, luminance), (R, G, B, dVCM) and, when a
+// normal test or vertex merging reads it, (nx, ny, nz, dVM): 32 or 48 bytes
 constexpr int PAY_VEC = 3;
+__host__ __device__ constexpr int pay_rec(bool nrm_or_vcm) { return nrm_or_vcm ? 3 : 2; }
+// photons of one gather launch: the byte offsets of its records (and of the point at infinity after
+// them) fit 32 bits
+constexpr int64_t max_batch_photons(int rec) { return (int64_t)(0xFFFFFFFFull / (16ull * rec)) - 2; }
 
 inline uint32_t max_cells_for(int64_t n_photons)
 {
@@ -186,7 +190,7 @@ struct WsLayout {
     int n_sets = 0;
     int ngs = 1;              // grid streams of the batch: min(sets, GRID_STREAMS)
     int64_t n_total = 0, h_total = 0, n_max = 0;
-    int64_t pstride = 0;      // payload plane entries: the batch's photons, then one point at infinity
+    int64_t pstride = 0;      // payload records: the batch's photons, then one point at infinity
     SortScratch sort[GRID_STREAMS];
     size_t cstart = 0, pay = 0;
     size_t flag = 0, ids = 0, tiles = 0, heavy = 0, light = 0, lcost = 0, counts = 0, desc = 0;
@@ -233,7 +237,7 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     }
     W.cstart = take(4 * (size_t)(cells + 1));
     W.pstride = W.n_total + 1;
-    W.pay = take(16 * (size_t)W.pstride * PAY_VEC + 256);
+    W.pay = take(16 * (size_t)W.pstride * PAY_VEC + 256);      // records of up to PAY_VEC float4s
     const size_t hk = 4 * (size_t)(W.h_total + 1);
     W.flag = take(hk);
     W.ids = take(hk);

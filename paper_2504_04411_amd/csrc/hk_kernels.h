@@ -19,15 +19,15 @@ struct KernelSrc {
     const float *cam_mis[3];
 };
 
-// Grid build of one set; its payload goes to pay + pay_off in each of the PAY_VEC planes of
-// pstride photons, its cell starts (set-local photon positions) to cstart.
+// Grid build of one set; its payload records go to records pay_off.. of the batch's payload, its cell
+// starts (set-local photon positions) to cstart.
 struct GridLaunch {
     SetHeader *hdr;
     PhotonSrc src;
     int64_t n;
     uint32_t *keyA, *keyB, *valA, *valB, *hist, *part, *part3, *cstart;
-    float4 *pay;             // the set's first (position, luminance) entry: plane base + pay_off
-    int64_t pstride;         // entries per plane: the (normal, flux) pairs start at plane base + pstride
+    float4 *pay;             // the batch's payload: record q at pay + q * rec
+    int rec;                 // float4s per record (pay_rec of the batch)
     int64_t pay_off;         // the set's first photon in the batch's payload
     uint32_t ncells_bound;   // cells of the plan never exceed this (workspace capacity)
 };
@@ -62,8 +62,8 @@ struct ListLaunch {
 // Everything the batched gather / test / update kernel needs besides the per-set table.
 struct BatchArgs {
     const SetDesc *desc;     // per-set table (device)
-    const float4 *pay;       // combined payload: plane v at pay + v * pstride
-    uint32_t pstride;        // the batch's photons, then (plane A only) one point at infinity
+    const float4 *pay;       // combined payload records (pay_rec(NRM || VCM) float4s each)
+    uint32_t pstride;        // records: the batch's photons, then one point at infinity
     const uint32_t *cstart;  // combined cell starts (set-local positions)
     const uint32_t *heavy, *light, *counts;   // work list, entries (set << Q_BITS) | kernel
     float k;
@@ -130,7 +130,7 @@ void launch_mlp_forward(const MlpView &M, const uint16_t *feat, int64_t n, float
 void launch_mlp_grad(const MlpView &M, const uint16_t *feat, const float *label, int64_t n, float *part, float *grad,
                      hipStream_t s);
 void launch_mlp_adam(const MlpView &M, const float *grad, float lr, hipStream_t s);
-void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, const float4 *pay, int64_t pstride,
+void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, const float4 *pay, int rec,
                      bool nrm_test, float cos_min, float it_code, uint16_t *feat, uint32_t *counts, hipStream_t s);
 void launch_propose(const StateView &st, int64_t H, const float *y, float margin, hipStream_t s);
 

@@ -346,7 +346,7 @@ void launch_mlp_adam(const MlpView &M, const float *grad, float lr, hipStream_t 
 constexpr int FEAT_WAVES = 4;
 
 __global__ __launch_bounds__(64 * FEAT_WAVES) void features_kernel(StateView st, int64_t H, const uint32_t *cstart,
-                                                                   const float4 *pay, int64_t pstride, int nrm_test,
+                                                                   const float4 *pay, int rec, int nrm_test,
                                                                    float cos_min, float it_code, uint16_t *feat,
                                                                    uint32_t *counts)
 {
@@ -376,12 +376,12 @@ __global__ __launch_bounds__(64 * FEAT_WAVES) void features_kernel(StateView st,
                     const uint32_t cell = ((uint32_t)cz * dimy + (uint32_t)cy) * dimx;
                     const uint32_t b0 = cstart[cell + (uint32_t)c0[0]], b1 = cstart[cell + (uint32_t)c1[0] + 1u];
                     for (uint32_t j = b0 + (uint32_t)lane; j < b1; j += 64u) {
-                        const float4 a = pay[j];
+                        const float4 a = pay[(int64_t)j * rec];
                         const float dx = p[0] - a.x, dy = p[1] - a.y, dz = p[2] - a.z;
                         const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                         if (!(d2 < R2[0])) continue;
                         if (nrm_test) {
-                            const float4 bn = pay[pstride + 2 * (int64_t)j];
+                            const float4 bn = pay[(int64_t)j * rec + 2];
                             const float cs = fmaf(nv[2], bn.z, fmaf(nv[1], bn.y, nv[0] * bn.x));
                             if (!(cs >= cos_min)) continue;
                         }
@@ -414,10 +414,10 @@ __global__ __launch_bounds__(64 * FEAT_WAVES) void features_kernel(StateView st,
     }
 }
 
-void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, const float4 *pay, int64_t pstride,
+void launch_features(const StateView &st, int64_t H, const uint32_t *cstart, const float4 *pay, int rec,
                      bool nrm_test, float cos_min, float it_code, uint16_t *feat, uint32_t *counts, hipStream_t s)
 {
-    features_kernel<<<(int)cdiv(H, FEAT_WAVES), 64 * FEAT_WAVES, 0, s>>>(st, H, cstart, pay, pstride, nrm_test ? 1 : 0,
+    features_kernel<<<(int)cdiv(H, FEAT_WAVES), 64 * FEAT_WAVES, 0, s>>>(st, H, cstart, pay, rec, nrm_test ? 1 : 0,
                                                                          cos_min, it_code, feat, counts);
 }
 
