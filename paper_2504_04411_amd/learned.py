@@ -199,17 +199,18 @@ def compare(est: Estimator, net: Network, w, batches, truth: torch.Tensor, margi
     return out
 
 
-def choose_margin(est: Estimator, net: Network, w, batches, truth, margins, set_id: int = 0):
-    """The margin whose learned run reaches the plain run's final MSE in the fewest iterations on a
-    validation scene (a deterministic criterion: timings would make the choice vary from run to
-    run); ties and misses fall back to the lowest final MSE."""
-    plain = _run(est, set_id, w, batches, truth)
+def choose_margin(est: Estimator, net: Network, scenes, margins, set_id: int = 0):
+    """The margin whose learned runs reach the plain runs' final MSE in the fewest iterations on the
+    validation scenes ((workload, batches, truth) each), averaged over the scenes with a miss
+    counted as one iteration past the end (a deterministic criterion: timings would make the choice
+    vary from run to run); ties go to the lowest mean final MSE."""
+    plains = [_run(est, set_id, w, b, t) for w, b, t in scenes]
     best, key_best, runs = None, None, {}
     for m in margins:
-        s = summarize(plain, _run(est, set_id, w, batches, truth, net, m))
-        runs[m] = s
-        key = (s["learned_iters_to_plain_final_mse"] is None, s["learned_iters_to_plain_final_mse"] or 0,
-               s["learned_final_mse"])
+        ss = [summarize(p, _run(est, set_id, w, b, t, net, m)) for p, (w, b, t) in zip(plains, scenes)]
+        runs[m] = ss
+        its = [s["learned_iters_to_plain_final_mse"] or (s["iterations"] + 1) for s in ss]
+        key = (float(np.mean(its)), float(np.mean([s["learned_final_mse"] for s in ss])))
         if key_best is None or key < key_best:
             best, key_best = m, key
     return best, runs
@@ -231,11 +232,12 @@ def he_init(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def experiment(est: Estimator, make_scene, train_seeds, val_seed, test_seeds, margins=(0.0, 0.5, 1.0, 1.5),
+def experiment(est: Estimator, make_scene, train_seeds, val_seeds, test_seeds,
+               margins=(0.5, 1.0, 1.5, 2.0, 2.5, 3.0),
                epoch_blocks: int = 4, epochs_per_block: int = 3, batch: int = 8192, lr: float = 2e-3,
                init_seed: int = 1, log=None):
     """Trains a network on plain runs of the training scenes (features at iterations 1, 2, 4, 8 ->
-    log(r_final / r1)), picks the proposal margin on the validation scene, and compares plain and
+    log(r_final / r1)), picks the proposal margin on the validation scenes, and compares plain and
     learned runs of each held-out test scene at equal MSE. make_scene(seed) -> (workload, device
     batches). The top-level comparison fields are those of the first test scene; `scenes` lists
     every test scene and `summary` their mean and spread; `train_gpu_ms` is the GPU time of the
@@ -273,10 +275,14 @@ def experiment(est: Estimator, make_scene, train_seeds, val_seed, test_seeds, ma
     train_mse, label_var = sq / rows, float(Y.var())
     say(f"trained: mse {train_mse:.4f} against label variance {label_var:.4f} ({steps} steps, {train_ms:.1f} ms)")
     del X, Y
-    wv, bv = make_scene(val_seed)
-    margin, val = choose_margin(est, net, wv, bv, truth_box(wv), margins)
-    del bv
-    say(f"margin {margin} chosen on scene {val_seed}")
+    vseeds = [val_seeds] if isinstance(val_seeds, int) else list(val_seeds)
+    vals = []
+    for sd in vseeds:
+        wv, bv = make_scene(sd)
+        vals.append((wv, bv, truth_box(wv)))
+    margin, val = choose_margin(est, net, vals, margins)
+    del vals
+    say(f"margin {margin} chosen on scenes {vseeds}")
     scenes = []
     for s in seeds:
         wt, bt = make_scene(s)
@@ -291,7 +297,7 @@ def experiment(est: Estimator, make_scene, train_seeds, val_seed, test_seeds, ma
     out = dict(scenes[0])
     out.update(margin=margin, train_mse=train_mse, label_var=label_var, train_rows=rows, train_steps=steps,
                train_gpu_ms=train_ms, features_gpu_ms=feat_ms)
-    out["validation"] = {str(m): {k: v for k, v in r.items()} for m, r in val.items()}
+    out["validation"] = {str(m): [{k: v for k, v in r.items()} for r in rs] for m, rs in val.items()}
     out["scenes"] = scenes
     sp = [r["speedup_to_plain_final_mse"] for r in scenes if r["speedup_to_plain_final_mse"]]
     its = [r["learned_iters_to_plain_final_mse"] for r in scenes if r["learned_iters_to_plain_final_mse"]]
