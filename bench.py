@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # Dominant-kernel VALU work model per launch (lane operations), the hot-path measurement model:
-# 150 per hit point (load state, F in float64, update), 35 per in-disk pair (map, group, compensated
+# 150 per hit point (load state, F in float64, update), 35 per in-disk pair (map, group, group
 # sums), 8 per candidate with 2.9 candidates per in-disk pair (uniform grid with cell = r).
 OPS_PER_QUERY = 150.0
 OPS_PER_PAIR = 35.0 + 8.0 * 2.9
@@ -42,7 +42,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 # Algorithmic bytes the gather / test / update must move per launch: every stored light vertex's
 # payload read once (P_b bytes) and every hit point's geometry read (G_h) and statistics read and
-# written once (2 x 232 bytes: twelve compensated (S, Q) pairs, the estimate pair, radius, counts).
+# written once (2 x 232 bytes: twelve float64 (S, Q) pairs, the estimate pair, radius, counts).
 STATE_RW = 2 * 232
 WORKLOADS = {
     "sets": dict(P_b=24, G_h=12),       # planar sets: position + flux; position

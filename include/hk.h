@@ -318,8 +318,8 @@ int hk_read_debug(hk_ctx *ctx, int set_id, const void *state, uint32_t *count, d
                   uint8_t *decision, uint32_t *t, hipStream_t stream);
 
 /* Retained group sums in float64 (device, row-major, original order): S and Q, n x 12 each with the
- * luminance test and n x 36 with one test per channel (column = channel * 12 + group), as the
- * compensated float32 pairs (value + collected rounding errors), and the estimate tau (n x 3). */
+ * luminance test and n x 36 with one test per channel (column = channel * 12 + group), as the state
+ * holds them, and the estimate tau (n x 3, a float32 value plus its collected rounding error). */
 int hk_read_sums(hk_ctx *ctx, int set_id, const void *state, double *S, double *Q, double *tau,
                  hipStream_t stream);
 

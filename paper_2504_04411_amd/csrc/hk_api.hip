@@ -1194,11 +1194,11 @@ __global__ void read_sums_kernel(StateView st, int64_t n, double *S, double *Q, 
     const size_t a = st.astride;
     const float *tv = st.tau0 + s;
     const int w = NG * st.nch;                  // columns: channel * NG + group
-    const float4 *sq = st.sq4 + (size_t)s * w;
+    const double2 *sq = st.sq2 + (size_t)s * w;
     for (int g = 0; g < w; ++g) {
-        const float4 x = sq[g];
-        if (S) S[(int64_t)j * w + g] = (double)x.x + (double)x.y;
-        if (Q) Q[(int64_t)j * w + g] = (double)x.z + (double)x.w;
+        const double2 x = sq[g];
+        if (S) S[(int64_t)j * w + g] = x.x;
+        if (Q) Q[(int64_t)j * w + g] = x.y;
     }
     if (tau)
         for (int c = 0; c < 3; ++c) tau[(int64_t)j * 3 + c] = (double)tv[(2 * c) * a] + (double)tv[(2 * c + 1) * a];

@@ -7,7 +7,7 @@
 // the x-range that can reach the disk. The G lanes walk the concatenated rows G photons at a time:
 // lane j takes the candidates at positions j, j + G, ... of the concatenation, loads each one's whole
 // payload (16-byte loads, four candidates in flight per lane), tests it against the disk and, when
-// it is inside, adds it at once to lane-private compensated sums kept in LDS. Each lane thus sums a
+// it is inside, adds it at once to lane-private float64 sums kept in LDS. Each lane thus sums a
 // fixed subsequence of the kernel's candidates, so a kernel's sums never depend on the other kernels
 // of its wave; at the end the G partial results are combined in a fixed order (deterministic) and
 // the kernel's epilogue runs. Nothing waits between the test and the accumulation: the only memory
@@ -25,8 +25,8 @@
 // Per pair inside the disk (Sec. 3.2, Sec. 5.1):
 //   y = (<x - x*, u>, <x - x*, v>)             (Eq. map-function)
 //   g = annulus (2 d2 >= r2) x sector (60 degree wedges from +u)
-//   S_g += psi, Q_g += psi^2                  (compensated float32 pairs, TwoSum / fma product)
-//   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1), Kahan-compensated
+//   S_g += psi, Q_g += psi^2                  (float64: the float32 sample and its square are exact)
+//   flux sum += Phi (PPM) or w * beta (vertex merging, Eq. mis-weight with beta = 1), float64
 // Epilogue per kernel: retained sums (Sec. 5.1), F in float64 (Eq. f-statistic) against the
 // tabulated critical value for m = sum of J over the kept iterations, estimate update
 // (Eq. progressive-VCM-estimator) with this iteration's radius, then Eq. radiusupdate.
@@ -53,21 +53,6 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-// Butterfly sum of the G lanes' compensated pairs (s, c): every step adds the partner's pair with an
-// exact TwoSum, whose error term does not depend on the order of the operands, so both partners
-// hold the same pair and the result does not depend on anything outside the kernel's lanes.
-template <int G>
-__device__ __forceinline__ void group_sum_pair(float &s, float &c)
-{
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        const float s2 = __shfl_xor(s, o, G);
-        const float c2 = __shfl_xor(c, o, G);
-        c = c + c2;
-        acc2(s, c, s2);
-    }
-}
-
 template <int G>
 __device__ __forceinline__ uint32_t group_sum_u(uint32_t v)
 {
@@ -90,7 +75,7 @@ constexpr uint32_t XCD_CHUNK = 64;  // work items per XCD chunk
 // channel.
 template <int CH>
 struct Lds {
-    float4 slot[NG * CH][WAVE];   // lane-private pairs (S, err S, Q, err Q) per channel and group
+    double2 slot[NG * CH][WAVE];  // lane-private sums (S, Q) per channel and group
     uint32_t dl[WAVE];            // row start, byte offset into the position plane
     uint32_t re[WAVE];            // row end (exclusive), byte offset into the position plane
 };
@@ -101,20 +86,9 @@ struct Query {
     float r2, inv_eta, wc, cb[3];
 };
 
-// Kahan's compensated sum: c carries the negated rounding error of the running sum s, so s - c tracks
-// the exact sum to within about 2u of its magnitude. Used for the flux sums, which feed the estimate
-// only; the test's group sums keep the exact-error pairs of acc2.
-__device__ __forceinline__ void kahan(float &s, float &c, float x)
-{
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
 // Accumulators of one lane.
 struct Acc {
-    float fR, cR, fG, cG, fB, cB;         // flux sums with their Kahan compensations
+    double fR, fG, fB;                    // flux sums
     uint32_t cnt;
 };
 
@@ -139,7 +113,8 @@ __device__ __forceinline__ Cand load_cand(uint32_t off, const float4 *rec)
 // Adds a candidate found inside the disk to this lane's group sums and flux sum when it passes the
 // normal-consistency test. The distance vector is recomputed with the same float32 operations as
 // in the test, so the values are those the test saw. A photon that fails the normal test is added
-// as zeros (an exact no-op on the pairs).
+// as zeros (an exact no-op). A float32 sample and its square are exact in float64, so each
+// addition rounds once at 2^-53 of the sum: one conversion, one add and one fma per sample.
 template <bool NRM, bool VCM, int CH>
 __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float cos_min, Lds<CH> &L, int lane,
                                            Acc &c)
@@ -176,24 +151,26 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
     }
     if (NRM && !ok) psi = wR = wG = wB = pR = pG = pB = 0.0f;
     if (CH == 1) {
-        float4 sv = L.slot[g][lane];
-        acc2(sv.x, sv.y, psi);
-        acc2_sq(sv.z, sv.w, psi);
+        double2 sv = L.slot[g][lane];
+        const double x = (double)psi;
+        sv.x += x;
+        sv.y = fma(x, x, sv.y);
         L.slot[g][lane] = sv;
     } else {
         // one test per channel (chromatic light): the channel's sample replaces the luminance
         const float pc[3] = {pR, pG, pB};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float4 sv = L.slot[ch * NG + g][lane];
-            acc2(sv.x, sv.y, pc[ch]);
-            acc2_sq(sv.z, sv.w, pc[ch]);
+            double2 sv = L.slot[ch * NG + g][lane];
+            const double x = (double)pc[ch];
+            sv.x += x;
+            sv.y = fma(x, x, sv.y);
             L.slot[ch * NG + g][lane] = sv;
         }
     }
-    kahan(c.fR, c.cR, wR);
-    kahan(c.fG, c.cG, wG);
-    kahan(c.fB, c.cB, wB);
+    c.fR += (double)wR;
+    c.fG += (double)wG;
+    c.fB += (double)wB;
     c.cnt += ok ? 1u : 0u;
 }
 
@@ -254,8 +231,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         K.cb[2] = fslot(SL_CB + 2)[q];
     }
 #pragma unroll
-    for (int g = 0; g < NG * CH; ++g) L.slot[g][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    Acc c = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+    for (int g = 0; g < NG * CH; ++g) L.slot[g][lane] = make_double2(0.0, 0.0);
+    Acc c = {0.0, 0.0, 0.0, 0u};
     uint32_t ncand = 0;                           // candidate tests of this kernel (all row batches)
 
     int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
@@ -327,18 +304,16 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     // count's J sums and critical value, and (first lane) the photons seen and the running estimate.
     constexpr int COLS = NG * CH;                 // column = channel * NG + group
     constexpr int CPL = (COLS + G - 1) / G;
-    float4 *const sq4 = reinterpret_cast<float4 *>(fslot(SL_SQ));   // per hit point, COLS float4s
-    float S[CPL], cS[CPL], Q[CPL], cQ[CPL];
+    double2 *const sq2 = reinterpret_cast<double2 *>(fslot(SL_SQ));   // per hit point, COLS (S, Q)
+    double S[CPL], Q[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
-        S[k] = cS[k] = Q[k] = cQ[k] = 0.0f;
+        S[k] = Q[k] = 0.0;
         if (active && col < COLS) {
-            const float4 x = sq4[(size_t)q * COLS + col];
+            const double2 x = sq2[(size_t)q * COLS + col];
             S[k] = x.x;
-            cS[k] = x.y;
-            Q[k] = x.z;
-            cQ[k] = x.w;
+            Q[k] = x.y;
         }
     }
     const uint32_t t_new = t_prev + 1u;
@@ -354,31 +329,23 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 
     // Combine the G lane partials: lane j of the kernel combines groups j, j + G, ... from LDS in
     // lane order (a whole-wavefront kernel: four lanes per group, 16 partials each, then a
-    // butterfly); the flux pairs are folded across the kernel's lanes by a butterfly.
-    float fR = c.fR, xR = -c.cR, fG = c.fG, xG = -c.cG, fB = c.fB, xB = -c.cB;   // pairs s + x
-    group_sum_pair<G>(fR, xR);
-    group_sum_pair<G>(fG, xG);
-    group_sum_pair<G>(fB, xB);
+    // butterfly); the flux sums are folded across the kernel's lanes by a butterfly (both partners
+    // of a step add the same two values, so they hold the same sum).
+    const double fR = group_sum<G>(c.fR), fG = group_sum<G>(c.fG), fB = group_sum<G>(c.fB);
     if constexpr (G == WAVE && COLS <= 16) {
         // the retained sums sit in lanes 0..COLS-1 (zero elsewhere) and enter once
         const int col = j & 15, sub = j >> 4;
         if (col < COLS) {
             for (int l = 0; l < 16; ++l) {
-                const float4 x = L.slot[col][base + sub * 16 + l];
-                acc2(S[0], cS[0], x.x);
-                cS[0] += x.y;
-                acc2(Q[0], cQ[0], x.z);
-                cQ[0] += x.w;
+                const double2 x = L.slot[col][base + sub * 16 + l];
+                S[0] += x.x;
+                Q[0] += x.y;
             }
         }
 #pragma unroll
         for (int o = 16; o < WAVE; o <<= 1) {
-            const float s2 = __shfl_xor(S[0], o, WAVE), c2 = __shfl_xor(cS[0], o, WAVE);
-            const float q2 = __shfl_xor(Q[0], o, WAVE), d2 = __shfl_xor(cQ[0], o, WAVE);
-            cS[0] = cS[0] + c2;
-            acc2(S[0], cS[0], s2);
-            cQ[0] = cQ[0] + d2;
-            acc2(Q[0], cQ[0], q2);
+            S[0] += __shfl_xor(S[0], o, WAVE);
+            Q[0] += __shfl_xor(Q[0], o, WAVE);
         }
     } else {
 #pragma unroll
@@ -386,11 +353,9 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
             const int col = j + k * G;
             if (col < COLS) {
                 for (int l = 0; l < G; ++l) {
-                    const float4 x = L.slot[col][base + l];
-                    acc2(S[k], cS[k], x.x);
-                    cS[k] += x.y;
-                    acc2(Q[k], cQ[k], x.z);
-                    cQ[k] += x.w;
+                    const double2 x = L.slot[col][base + l];
+                    S[k] += x.x;
+                    Q[k] += x.y;
                 }
             }
         }
@@ -406,8 +371,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
         const bool grp = col < COLS;
-        sg[k] = grp ? (double)S[k] + (double)cS[k] : 0.0;
-        qg[k] = grp ? (double)Q[k] + (double)cQ[k] : 0.0;
+        sg[k] = grp ? S[k] : 0.0;
+        qg[k] = grp ? Q[k] : 0.0;
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) tl[ch] += (grp && col / NG == ch) ? sg[k] : 0.0;
     }
@@ -430,7 +395,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         ssb[ch] = group_sum<G>(bl[ch]) / m;
         ssw[ch] = group_sum<G>(wl[ch]);
     }
-    const float flR = fR + xR, flG = fG + xG, flB = fB + xB;
+    const float flR = (float)fR, flG = (float)fG, flB = (float)fB;
 
     int shrink = 0;
     if (active && j == 0) {
@@ -471,8 +436,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     for (int k = 0; k < CPL; ++k) {
         const int col = j + k * G;
         if (active && col < COLS)
-            sq4[(size_t)q * COLS + col] = shrink ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
-                                                 : make_float4(S[k], cS[k], Q[k], cQ[k]);
+            sq2[(size_t)q * COLS + col] = shrink ? make_double2(0.0, 0.0) : make_double2(S[k], Q[k]);
     }
     __syncthreads();
 }

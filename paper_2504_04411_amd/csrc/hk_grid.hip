@@ -661,7 +661,7 @@ __device__ void init_one(const KernelSrc &src, const StateView &st, const uint32
     st.cnt[s] = 0;
     st.dec[s] = 0;
     st.cand[s] = 0;
-    for (int i = 0; i < NG * st.nch; ++i) st.sq4[(size_t)s * (NG * st.nch) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int i = 0; i < NG * st.nch; ++i) st.sq2[(size_t)s * (NG * st.nch) + i] = make_double2(0.0, 0.0);
     for (int i = 0; i < 6; ++i) st.tau0[(size_t)i * st.astride + s] = 0.0f;
     st.F[s] = NAN;
     st.Fc[s] = NAN;

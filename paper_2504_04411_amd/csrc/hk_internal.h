@@ -9,7 +9,7 @@
 namespace hk {
 
 constexpr int NG = 12;              // 2 annuli x 6 sectors (Sec. 6.1.1)
-constexpr int NSQ = 4 * NG;         // per group: S, comp(S), Q, comp(Q)
+constexpr int NSQ = 4 * NG;         // per group: S and Q as float64 (four float-sized slots)
 constexpr int RHIST_BINS = 64;      // radius histogram: bin = floor(-4 log2(r / r1))
 constexpr uint32_t KEY_OUTSIDE = 0xFFFFFFu;   // cell key of a photon outside the grid domain
 constexpr uint32_t MAX_CELLS = 0xFFFFF0u;     // keys fit 24 bits: three 8-bit radix passes
@@ -100,8 +100,8 @@ struct StateView {
     float *r;
     uint32_t *t, *nseen, *orig, *cnt, *dec;
     uint32_t *cand;      // candidate tests of the last iteration (the next work list's cost estimate)
-    float *sq0;          // group sums: NSQ * nch slots holding, per hit point s, NG * nch float4s
-    float4 *sq4;         // (S, err S, Q, err Q) at sq4[s * NG * nch + column], column = channel * NG + group
+    float *sq0;          // group sums: NSQ * nch slots holding, per hit point s, NG * nch double2s
+    double2 *sq2;        // (S, Q) at sq2[s * NG * nch + column], column = channel * NG + group
     int nch;             // test channels
     float *tau0;         // estimate: array c at tau0 + c * astride
     uint32_t astride;    // floats between slots
@@ -134,7 +134,7 @@ inline StateView make_view(void *base, const Layout &L)
     s.dec = u(SL_DEC);
     s.cand = u(SL_CAND);
     s.sq0 = f(SL_SQ);
-    s.sq4 = reinterpret_cast<float4 *>(s.sq0);
+    s.sq2 = reinterpret_cast<double2 *>(s.sq0);
     s.nch = L.nch;
     s.tau0 = f(SL_TAU);
     s.astride = (uint32_t)(L.stride / sizeof(float));
@@ -301,15 +301,6 @@ __device__ __forceinline__ void acc2(float &s, float &c, float x)
     const float e = (s - (t - z)) + (x - z);
     s = t;
     c += e;
-}
-
-// Adds x^2 to the pair exactly up to the pair's own rounding: the product's error comes from an fma
-// (x * x = p + fma(x, x, -p) exactly).
-__device__ __forceinline__ void acc2_sq(float &s, float &c, float x)
-{
-    const float p = x * x;
-    acc2(s, c, p);
-    c += fmaf(x, x, -p);
 }
 
 // Grid cells overlapping [p - r - margin, p + r + margin] on every axis; false if none.

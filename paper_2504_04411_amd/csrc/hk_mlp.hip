@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) void propose_kernel(StateView st, int64_t H, c
             st.t[q] = 0u;
             st.nseen[q] = 0u;
             for (int i = 0; i < NG * st.nch; ++i)
-                st.sq4[(size_t)q * (NG * st.nch) + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                st.sq2[(size_t)q * (NG * st.nch) + i] = make_double2(0.0, 0.0);
         }
         atomicAdd(&hist[radius_bin(rp, r1)], 1u);
     }

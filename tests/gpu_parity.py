@@ -5,14 +5,17 @@ Rules (parity bar):
   * shrink decisions: exact, except where the oracle's |F - Fc| < 1e-6 (either outcome is correct);
     a kernel whose decision differs inside that band leaves the comparison from then on;
   * radii: bit-exact for kernels still compared (both sides update in float32);
-  * F: per kernel, |dF| <= max(1, F) (2 sqrt(n / 132) + 2) n u^2 + 1e-13, with n the samples in the
-    retained sums (u = 2^-24). The group sums are float32 pairs updated by TwoSum (and an fma split
-    of psi^2), whose only rounding is that of the error word c, at most u |c| <= u^2 |S| per
-    addition, so each of the 12 group sums is off by at most n u^2 of its value. F's sensitivity to
-    such relative errors is about 2 S_g / sqrt(sum_g d_g^2) through the between-group term
-    (d_g = S_g - mean; near the null hypothesis this is 2 sqrt(n_g / 11) with n_g = n / 12 samples
-    per group) plus about 2 through the within-group term; 1e-13 covers F's own float64
-    evaluation. At the workloads' sizes this stays below 1e-8, far inside the 1e-6 decision band;
+  * F: per kernel, |dF| <= max(1, F) (2 sqrt(n / 132) + 2) (2 n + 65 k) e + 1e-13, with n the
+    samples in the retained sums, k the iterations so far and e = 2^-53. The group sums are float64
+    on both sides: a float32 sample and its square are exact in float64, and each addition of a
+    nonnegative term rounds by at most e of the running sum, so a kernel's group sum that took at
+    most n samples, 64 lane partials and one retained sum per iteration is off by at most
+    (n + 65 k) e of its value, the oracle's by at most n e. F's
+    sensitivity to such relative errors is about 2 S_g / sqrt(sum_g d_g^2) through the
+    between-group term (d_g = S_g - mean; near the null hypothesis this is 2 sqrt(n_g / 11) with
+    n_g = n / 12 samples per group) plus about 2 through the within-group term; 1e-13 covers F's
+    own float64 evaluation. At the workloads' sizes this stays below 1e-10, far inside the 1e-6
+    decision band;
   * critical values: relative 1e-10;
   * radiance: relative 1e-5.
 """
@@ -112,8 +115,9 @@ class Tracker:
                                 f"{rg[badr[:5]]} vs {ost.r[badr[:5]]}")
         n_ret = (self.nseen + ost.count).astype(np.float64)
         self.nseen = ost.nseen.astype(np.int64).copy()
-        u = 2.0 ** -24
-        tol = np.maximum(1.0, np.abs(ost.F)) * (2.0 * np.sqrt(n_ret / 132.0) + 2.0) * n_ret * u * u + 1e-13
+        e = 2.0 ** -53
+        adds = 2.0 * n_ret + 65.0 * (it + 1)
+        tol = np.maximum(1.0, np.abs(ost.F)) * (2.0 * np.sqrt(n_ret / 132.0) + 2.0) * adds * e + 1e-13
         dF = np.abs(d["F"] - ost.F)
         badF = np.flatnonzero(alive & np.isfinite(ost.F) & ~(dF <= tol))
         assert badF.size == 0, (f"[{self.name}] iteration {it + 1}: F beyond its rounding bound at {idx[badF[:5]]}: "

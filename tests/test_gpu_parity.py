@@ -138,15 +138,15 @@ def test_determinism_bitwise():
         assert np.array_equal(a, b)
 
 
-def test_compensated_sums_error_against_float64():
-    """Retained group sums and the estimate from the compensated float32 pairs against the float64
-    oracle after 16 iterations of config 0 (sums of float32 samples are exact in float64 here).
+def test_group_sums_error_against_float64_oracle():
+    """Retained group sums and the estimate against the oracle after 16 iterations of config 0.
 
-    Bound: every addition to a pair (s, c) splits s + x exactly into t + e (TwoSum) and adds e to c;
-    squared samples enter as their exact fma split. The only rounding left is c's own, at most
-    u |c| <= u^2 |S| per addition, so after N additions |dS| <= N u^2 sum|x| (u = 2^-24); with
-    nonnegative samples sum|x| = S. N is at most 16 iterations x 100k photons. The estimate adds a
-    float32 quotient per iteration (a few u relative each)."""
+    Bound: the group sums are float64 on both sides, the float32 samples and their squares exact in
+    float64, and every addition of a nonnegative term rounds by at most e = 2^-53 of the running sum.
+    A kernel's sum takes at most N = 16 x 100k samples, 64 lane partials and one retained sum per
+    iteration, the oracle's at most N samples, so |dS| <= (2 N + 65 x 16) e S. The estimate is a
+    compensated float32 pair updated once per iteration with a float32 quotient (a few u = 2^-24
+    relative each)."""
     from oracle import oracle as O
     from paper_2504_04411_amd.estimator import DevicePhotons, Estimator
     G = _G()
@@ -163,11 +163,10 @@ def test_compensated_sums_error_against_float64():
     eS = np.abs(S - st.S)[same].max() / max(np.abs(st.S[same]).max(), 1e-300)
     eQ = np.abs(Q - st.Q)[same].max() / max(np.abs(st.Q[same]).max(), 1e-300)
     rel_tau = (np.abs(tau - st.tau) / np.maximum(np.abs(st.tau), 1e-300))[same].max()
-    print(f"compensated float32 vs float64: max |dS|/max|S| = {eS:.3e}, |dQ|/max|Q| = {eQ:.3e}, "
+    print(f"float64 group sums vs the oracle: max |dS|/max|S| = {eS:.3e}, |dQ|/max|Q| = {eQ:.3e}, "
           f"max rel tau = {rel_tau:.3e}", flush=True)
-    u = 2.0 ** -24
-    bound = 16 * 100_000 * u * u
-    assert eS < bound and eQ < bound and rel_tau < 1e-6
+    bound = (2 * 16 * 100_000 + 65 * 16) * 2.0 ** -53
+    assert eS <= bound and eQ <= bound and rel_tau < 1e-6
     est.close()
 
 
