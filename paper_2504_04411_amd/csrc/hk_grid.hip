@@ -3,8 +3,8 @@
 //
 //   plan      picks the cell size from the radius distribution of the previous update
 //   keys      cell index of every photon (x fastest), KEY_OUTSIDE outside the grid domain
-//   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-block histograms,
-//             per-digit prefix over the blocks and digit totals, and a wave-ballot stable scatter
+//   sort      stable LSD radix sort of (key, photon index), 8-bit digits, per-chunk histograms, one
+//             exclusive scan over them (digit-major), and a wave-ballot stable scatter
 //   permute   the last sort pass writes the inverse permutation; a coalesced read / scattered write
 //             of the photon payload into sorted order, one contiguous record per photon:
 //             (position, luminance), (flux, dVCM) and, when read, (normal, dVM)
@@ -141,12 +141,24 @@ constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_CHUNK = 64 * RS_ITEMS;
 static_assert(RS_TILE == RS_WAVES * RS_CHUNK, "a radix block is its waves' chunks");
 
+// Workgroups are dealt to the 8 XCDs round-robin. A radix launch has 8 * per workgroups, and
+// workgroup b takes block (b mod 8) * per + b / 8: each XCD walks one contiguous range of blocks, so
+// the short runs that neighbouring chunks write into each digit's range (and their histogram
+// columns) fill whole cache lines in one L2 instead of partial lines in several. Returns -1 for
+// the padding workgroups past the last block.
+__host__ __device__ constexpr int rs_per_xcd(int nblk) { return (nblk + 7) / 8; }
+__device__ __forceinline__ int rs_block(int nblk)
+{
+    const int b = (int)blockIdx.x, blk = (b & 7) * rs_per_xcd(nblk) + (b >> 3);
+    return blk < nblk ? blk : -1;
+}
+
 // Digit counts of every segment of the block: hist[d * nseg + seg]. The chunk's keys are loaded
 // together (RS_ITEMS loads in flight per lane), then counted in the wave's own LDS histogram.
-__device__ __forceinline__ void rs_count_store(uint32_t (&cnt)[RS_WAVES][256], uint32_t *hist, int nseg)
+__device__ __forceinline__ void rs_count_store(uint32_t (&cnt)[RS_WAVES][256], uint32_t *hist, int nseg, int blk)
 {
     __syncthreads();
-    const int seg0 = blockIdx.x * RS_WAVES;
+    const int seg0 = blk * RS_WAVES;
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) {
         const int w = i & (RS_WAVES - 1), d = i / RS_WAVES;
         if (seg0 + w < nseg) hist[(int64_t)d * nseg + seg0 + w] = cnt[w][d];
@@ -154,42 +166,28 @@ __device__ __forceinline__ void rs_count_store(uint32_t (&cnt)[RS_WAVES][256], u
 }
 
 __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *keys, int64_t n, int shift,
-                                                             uint32_t *hist, int nseg)
+                                                             uint32_t *hist, int nseg, int nblk)
 {
     __shared__ uint32_t cnt[RS_WAVES][256];
+    const int blk = rs_block(nblk);
+    if (blk < 0) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0u;
     __syncthreads();
-    const int64_t base = ((int64_t)blockIdx.x * RS_WAVES + w) * RS_CHUNK + lane;
+    const int64_t base = ((int64_t)blk * RS_WAVES + w) * RS_CHUNK + lane;
     uint32_t k[RS_ITEMS];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) k[i] = base + 64 * i < n ? keys[base + 64 * i] : 0u;
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i)
         if (base + 64 * i < n) atomicAdd(&cnt[w][(k[i] >> shift) & 255u], 1u);
-    rs_count_store(cnt, hist, nseg);
+    rs_count_store(cnt, hist, nseg, blk);
 }
 
-// One block per digit d: the segments' counts of d become their exclusive prefix over the segments
-// (in place), and the digit's total goes to dtot[d].
-__global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nseg, uint32_t *dtot)
-{
-    uint32_t *h = hist + (int64_t)blockIdx.x * nseg;
-    uint32_t carry = 0;
-    for (int base = 0; base < nseg; base += 256) {
-        const int k = base + threadIdx.x;
-        const uint32_t v = k < nseg ? h[k] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
-        if (k < nseg) h[k] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
-}
-
-// Stable scatter, one wavefront per segment and no barrier between the block's waves. The wave's
-// first position for digit d is the exclusive scan of the digit totals at d plus the segment's
-// prefix within d, kept in the wave's own LDS row; the chunk is visited in rounds of 64 consecutive
+// Stable scatter, one wavefront per segment and no barrier between the block's waves. The counts
+// hist[d * nseg + seg], scanned as one array (digit-major), give each segment's first position for
+// digit d: all keys of smaller digits, then those of digit d in earlier segments. The wave keeps them
+// in its own LDS row; the chunk is visited in rounds of 64 consecutive
 // keys, a key's rank among the round's equal digits comes from eight ballots, and the first lane of
 // each digit then advances the row by the digit's count in the round (a wave's LDS accesses are
 // performed in order, so the next round reads the advanced value).
@@ -198,25 +196,17 @@ __global__ __launch_bounds__(256) void rs_offsets_kernel(uint32_t *hist, int nse
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
                                                                 uint32_t *kout, uint32_t *vout, int64_t n,
                                                                 int shift, const uint32_t *offs, int nseg,
-                                                                const uint32_t *dtot, uint32_t *inv)
+                                                                int nblk, uint32_t *inv)
 {
     __shared__ uint32_t row[RS_WAVES][256];
+    const int blk = rs_block(nblk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int seg = blockIdx.x * RS_WAVES + w;
-    if (seg >= nseg) return;
-    // digit bases: four digits per lane, an exclusive scan over the lanes
-    uint32_t t[4], sum = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        t[j] = dtot[4 * lane + j];
-        sum += t[j];
-    }
-    uint32_t ex = wave_incl_scan(sum) - sum;
+    const int seg = blk * RS_WAVES + w;
+    if (blk < 0 || seg >= nseg) return;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int d = 4 * lane + j;
-        row[w][d] = ex + offs[(int64_t)d * nseg + seg];
-        ex += t[j];
+        row[w][d] = offs[(int64_t)d * nseg + seg];
     }
     const int64_t base = (int64_t)seg * RS_CHUNK + lane;
     uint32_t k[RS_ITEMS], v[RS_ITEMS];
@@ -263,13 +253,15 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
 {
     const int nblk = (int)cdiv(n, RS_TILE);
     const int nseg = (int)cdiv(n, RS_CHUNK);
+    const int grid = 8 * rs_per_xcd(nblk);
     uint32_t *ki = kA, *vi = nullptr, *ko = kB, *vo = vB;
     uint32_t *vspare = vA;
     for (int shift = 0; shift < bits; shift += 8) {
         const bool last = shift + 8 >= bits;
-        if (shift > 0 || !first_hist_done) rs_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, n, shift, hist, nseg);
-        rs_offsets_kernel<<<256, 256, 0, s>>>(hist, nseg, part);
-        rs_scatter_kernel<<<nblk, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nseg, part,
+        if (shift > 0 || !first_hist_done)
+            rs_hist_kernel<<<grid, RS_THREADS, 0, s>>>(ki, n, shift, hist, nseg, nblk);
+        excl_scan(hist, (int64_t)256 * nseg, part, s, nullptr, 0);
+        rs_scatter_kernel<<<grid, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nseg, nblk,
                                                       (last && inverse) ? vo : nullptr);
         uint32_t *kt = ki;
         ki = ko;
@@ -422,14 +414,16 @@ __device__ __forceinline__ uint32_t cell_key(const GridPlan &g, float x, float y
 // of its RS_ITEMS keys together.
 __global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *hdr, const float *px,
                                                                const float *py, const float *pz, int64_t n,
-                                                               uint32_t *keys, uint32_t *hist, int nseg)
+                                                               uint32_t *keys, uint32_t *hist, int nseg, int nblk)
 {
     __shared__ uint32_t cnt[RS_WAVES][256];
+    const int blk = rs_block(nblk);
+    if (blk < 0) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&cnt[0][0])[i] = 0u;
     const GridPlan gp = grid_plan(hdr);
     __syncthreads();
-    const int64_t base = ((int64_t)blockIdx.x * RS_WAVES + w) * RS_CHUNK + lane;
+    const int64_t base = ((int64_t)blk * RS_WAVES + w) * RS_CHUNK + lane;
     float x[RS_ITEMS], y[RS_ITEMS], z[RS_ITEMS];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
@@ -448,7 +442,7 @@ __global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *
             atomicAdd(&cnt[w][key & 255u], 1u);
         }
     }
-    rs_count_store(cnt, hist, nseg);
+    rs_count_store(cnt, hist, nseg, blk);
 }
 
 // inv[original index] = sorted position
@@ -521,8 +515,9 @@ void build_grid(const GridLaunch &g, hipStream_t s)
     if (n > 0) {
         const int nb = (int)cdiv(n, 256);
         const int nblk = (int)cdiv(n, RS_TILE);
-        keys_hist_kernel<<<nblk, RS_THREADS, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1], g.src.pos[2], n, g.keyA,
-                                                      g.hist, (int)cdiv(n, RS_CHUNK));
+        keys_hist_kernel<<<8 * rs_per_xcd(nblk), RS_THREADS, 0, s>>>(g.hdr, g.src.pos[0], g.src.pos[1],
+                                                                      g.src.pos[2], n, g.keyA, g.hist,
+                                                                      (int)cdiv(n, RS_CHUNK), nblk);
         uint32_t *ks, *inv;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true, true);
         permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay + g.pay_off * g.rec, g.rec);

@@ -231,8 +231,7 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
         S.valB = take(4 * (size_t)nmax);
         const int64_t nblk = cdiv(nmax, RS_TILE);
         S.hist = take(4 * (size_t)(256 * (RS_TILE / 64) * nblk));      // per digit and wavefront chunk
-        const int64_t nscan = cdiv(256 * nblk, SCAN_TILE) + 1;
-        S.part = take(4 * (size_t)(nscan > 256 ? nscan : 256));   // scan partials, or the 256 digit totals
+        S.part = take(4 * (size_t)(cdiv(256 * (RS_TILE / 64) * nblk, SCAN_TILE) + 1));   // its scan's partials
         S.part3 = take(4 * (size_t)(cdiv((int64_t)MAX_CELLS + 2, SCAN_TILE) + 1));
     }
     W.cstart = take(4 * (size_t)(cells + 1));
