@@ -335,9 +335,11 @@ double hk_f_quantile(double d1, double d2, double alpha);
 /* Timing of the hk_iterate calls since enabling (hipEvents on the caller's stream; graphs are not
  * timed): hk_profile_enable(ctx, 1) starts recording, hk_profile_read(ctx, out, n) synchronises on
  * the last event and writes up to n values: phase totals in milliseconds [0] iteration plans and
- * grid builds, [1] wait for the critical values beyond the grid builds (they run on a second stream
- * beside them), [2] work list and set table, [3] the gather / test / update kernel alone, [4] radius
- * histogram and pair tally; then [5] the number of gather launches timed. */
+ * grid builds (of a batch's second gather phase, the part not hidden behind the first gather),
+ * [1] wait for the critical values beyond the grid builds (they run on a second stream beside them),
+ * [2] work lists and set table, [3] the gather / test / update launches alone, [4] radius histogram
+ * and pair tally; then [5] the number of gather launches timed (two per batch of two or more sets:
+ * the second phase's grids are built while the first phase's gather runs). */
 int hk_profile_enable(hk_ctx *ctx, int on);
 int hk_profile_read(hk_ctx *ctx, double *out, int n);
 

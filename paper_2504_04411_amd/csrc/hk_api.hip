@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -101,7 +102,7 @@ struct hk_ctx {
     hipStream_t aux = nullptr;     // second stream: critical values run beside the grid builds
     hipEvent_t fork = nullptr, join = nullptr;
     hipStream_t gs[GRID_STREAMS] = {};    // streams 1.. of the grid builds (stream 0 is the caller's)
-    hipEvent_t gfork = nullptr, gjoin[GRID_STREAMS] = {};
+    hipEvent_t gfork = nullptr, gjoin[GRID_STREAMS] = {}, gjoin2[GRID_STREAMS] = {};
 };
 
 struct hk_graph {
@@ -217,6 +218,7 @@ extern "C" int hk_destroy(hk_ctx *ctx)
     for (int g = 0; g < GRID_STREAMS; ++g) {
         if (ctx->gs[g]) (void)hipStreamDestroy(ctx->gs[g]);
         if (ctx->gjoin[g]) (void)hipEventDestroy(ctx->gjoin[g]);
+        if (ctx->gjoin2[g]) (void)hipEventDestroy(ctx->gjoin2[g]);
     }
     if (ctx->gfork) (void)hipEventDestroy(ctx->gfork);
     delete ctx;
@@ -433,7 +435,46 @@ static std::vector<std::vector<int>> make_batches(const hk_ctx *ctx, int n_sets,
         }
         if (!cur.empty()) out.push_back(cur);
     }
+    // within a batch, sets with more hit points per stored light vertex first: the gather's work
+    // grows with the hit points and the grid build's with the light vertices, so the batch's first
+    // gather phase takes the sets whose grids are cheap and whose gathers are long (phase_split)
+    for (auto &b : out)
+        std::stable_sort(b.begin(), b.end(), [&](int x, int y) {
+            const double hx = (double)ctx->sets[set_ids[x]].H, hy = (double)ctx->sets[set_ids[y]].H;
+            return hx * (double)(ph[y].n_stored + 1) > hy * (double)(ph[x].n_stored + 1);
+        });
     return out;
+}
+
+// Where a batch's second gather phase begins (nb: a single phase). The grids of the second phase's
+// sets are built on the grid streams while the first phase's gather runs, so an iteration takes
+// about grid(A) + max(gather(A), grid(B)) + gather(B) instead of the sum of all four. Model: a
+// grid costs its light vertices, a gather GATHER_PER_HIT light-vertex units per hit point (the ratio
+// of the two phases' times per unit on the uneven planar sets), a second phase PHASE_COST units
+// (its work list, launch and tail); the split with the lowest modelled time wins.
+static int phase_split(const hk_ctx *ctx, const std::vector<int> &b, const int *set_ids, const hk_photons *ph,
+                       int ngs)
+{
+    constexpr double GATHER_PER_HIT = 18.0, PHASE_COST = 1.2e6;
+    const int nb = (int)b.size();
+    if (nb < 2 || ngs < 2) return nb;
+    double grid_all = 0.0, gath_all = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        grid_all += (double)ph[b[k]].n_stored;
+        gath_all += GATHER_PER_HIT * (double)ctx->sets[set_ids[b[k]]].H;
+    }
+    int best = nb;
+    double best_t = grid_all + gath_all, grid_a = 0.0, gath_a = 0.0;
+    for (int kb = 1; kb < nb; ++kb) {
+        grid_a += (double)ph[b[kb - 1]].n_stored;
+        gath_a += GATHER_PER_HIT * (double)ctx->sets[set_ids[b[kb - 1]]].H;
+        const double t = grid_a + std::max(gath_a, grid_all - grid_a) + (gath_all - gath_a) + PHASE_COST;
+        if (t < best_t) {
+            best_t = t;
+            best = kb;
+        }
+    }
+    return best;
 }
 
 static WsLayout batch_layout(const hk_ctx *ctx, const std::vector<int> &b, const int *set_ids, const hk_photons *ph)
@@ -469,6 +510,7 @@ static int ensure_streams(hk_ctx *ctx)
     for (int g = 1; g < GRID_STREAMS; ++g) {
         if (!ctx->gs[g]) HIP_TRY(hipStreamCreateWithFlags(&ctx->gs[g], hipStreamNonBlocking));
         if (!ctx->gjoin[g]) HIP_TRY(hipEventCreateWithFlags(&ctx->gjoin[g], hipEventDisableTiming));
+        if (!ctx->gjoin2[g]) HIP_TRY(hipEventCreateWithFlags(&ctx->gjoin2[g], hipEventDisableTiming));
     }
     return HK_OK;
 }
@@ -523,13 +565,11 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(ctx->join, ctx->aux));
         // 3. per set: sort the photons into the grid; the sets' builds are independent and run on
-        //    W.ngs streams at once (set k on stream k mod ngs, stream 0 the caller's), joined before
-        //    the work list
-        if (W.ngs > 1) {
-            HIP_TRY(hipEventRecord(ctx->gfork, stream));
-            for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(ctx->gs[gi], ctx->gfork, 0));
-        }
-        for (int k = 0; k < nb; ++k) {
+        //    W.ngs streams at once. The first phase's sets (k < kb) use every grid stream (set k on
+        //    stream k mod ngs, stream 0 the caller's) and are joined before the first gather; the
+        //    second phase's sets follow on streams 1.. and are built while the first gather runs.
+        const int kb = phase_split(ctx, b, set_ids, ph, W.ngs);
+        auto grid_of = [&](int k, hipStream_t gstream, int gs) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
             const hk_photons &P = ph[s];
@@ -543,7 +583,6 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
                 g.src.mis[a] = vcm ? P.mis[a] : nullptr;
             }
             g.n = P.n_stored;
-            const int gs = k % W.ngs;                 // grid stream of this set
             const SortScratch &SS = W.sort[gs];
             g.keyA = reinterpret_cast<uint32_t *>(w + SS.keyA);
             g.keyB = reinterpret_cast<uint32_t *>(w + SS.keyB);
@@ -557,43 +596,38 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             g.rec = rec;
             g.pay_off = W.pay_off[k];
             g.ncells_bound = W.max_cells[k];
-            build_grid(g, gs == 0 ? stream : ctx->gs[gs]);
+            build_grid(g, gstream);
+        };
+        if (W.ngs > 1) {
+            HIP_TRY(hipEventRecord(ctx->gfork, stream));
+            for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(ctx->gs[gi], ctx->gfork, 0));
+        }
+        for (int k = 0; k < kb; ++k) {
+            const int gs = k % W.ngs;
+            grid_of(k, gs == 0 ? stream : ctx->gs[gs], gs);
         }
         for (int gi = 1; gi < W.ngs; ++gi) {
             HIP_TRY(hipEventRecord(ctx->gjoin[gi], ctx->gs[gi]));
             HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin[gi], 0));
         }
+        for (int k = kb; k < nb; ++k) {
+            const int gs = 1 + (k - kb) % (W.ngs - 1);
+            grid_of(k, ctx->gs[gs], gs);
+        }
+        if (kb < nb)
+            for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipEventRecord(ctx->gjoin2[gi], ctx->gs[gi]));
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
         HIP_TRY(hipStreamWaitEvent(stream, ctx->join, 0));
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
-        // 4. one work list over the batch, the set table, one gather / test / update launch, then the
-        //    radius histograms and pair counts of the batch's sets
+        // 4. per phase: the work list over the phase's sets, one gather / test / update launch; the
+        //    set table once before the first; then the radius histograms and pair counts of the batch
         uint32_t *flag = reinterpret_cast<uint32_t *>(w + W.flag);
         uint32_t *ids = reinterpret_cast<uint32_t *>(w + W.ids);
-        uint32_t *tiles = reinterpret_cast<uint32_t *>(w + W.tiles);
-        launch_zero(tiles, cdiv(W.h_total, SPLIT_TILE), stream);
         SetDesc desc[MAX_BATCH];
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
             const Layout L = layout_of(ctx, S.H);
-            const StateView st = make_view(state[s], L);
-            ListLaunch l{};
-            l.H = S.H;
-            l.hdr = st.hdr;
-            l.cstart = ws_cstart + W.cell_base[k];
-            for (int a = 0; a < 3; ++a) l.kp[a] = st.pos[a];
-            l.r = st.r;
-            l.cand = st.cand;
-            l.dec = st.dec;
-            l.k2 = p.k * p.k;
-            l.heavy_cost = (uint32_t)p.heavy_cost;
-            l.set_slot = (uint32_t)k;
-            l.q_base = (uint32_t)W.q_off[k];
-            l.flag = flag + W.q_off[k];
-            l.ids = ids + W.q_off[k];
-            l.tile_heavy = tiles;
-            launch_cost(l, stream);
             SetDesc &d = desc[k];
             memset(&d, 0, sizeof d);
             d.state = static_cast<char *>(state[s]);
@@ -608,28 +642,71 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             d.lbtab = L.lbtab;
             d.hdr = L.hdr;
         }
-        uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy);
-        uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light);
-        uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts);
-        launch_split(flag, ids, W.h_total, (uint32_t)p.heavy_cost, tiles, heavy, light,
-                     reinterpret_cast<uint32_t *>(w + W.lcost), counts, ws_pay + W.n_total * rec, stream);
         SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
-        launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
-        BatchArgs a{};
-        a.desc = table;
-        a.pay = ws_pay;
-        a.pstride = (uint32_t)W.pstride;
-        a.cstart = ws_cstart;
-        a.heavy = heavy;
-        a.light = light;
-        a.counts = counts;
-        a.k = p.k;
-        a.cos_min = p.normal_cos_min;
-        a.lanes_light = p.lanes_light;
-        a.lanes_heavy = p.lanes_heavy;
-        if (pe) HIP_TRY(hipEventRecord(pe->e[3], stream));
-        launch_gather(a, W.h_total, nrm_test, vcm, channels(ctx), stream);
-        if (pe) HIP_TRY(hipEventRecord(pe->e[4], stream));
+        for (int ph_i = 0; ph_i < 2; ++ph_i) {
+            const int k0 = ph_i == 0 ? 0 : kb, k1 = ph_i == 0 ? kb : nb;
+            if (k0 >= k1) continue;
+            if (ph_i == 1) {
+                // the second phase: its own profile record from here (its grids' wait, list, gather)
+                if (pe) {
+                    HIP_TRY(hipEventRecord(pe->e[5], stream));
+                    pe = prof_slot(ctx);
+                    if (!pe) return fail(HK_E_HIP, "hipEventCreate failed");
+                    HIP_TRY(hipEventRecord(pe->e[0], stream));
+                }
+                for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin2[gi], 0));
+                if (pe) {
+                    HIP_TRY(hipEventRecord(pe->e[1], stream));
+                    HIP_TRY(hipEventRecord(pe->e[2], stream));
+                }
+            }
+            const uint32_t q0 = W.q_off[k0];
+            const int64_t hp = (k1 < nb ? (int64_t)W.q_off[k1] : W.h_total) - q0;   // the phase's entries
+            uint32_t *tiles = reinterpret_cast<uint32_t *>(w + W.tiles) + (ph_i == 0 ? 0 : cdiv(q0, SPLIT_TILE) + 1);
+            launch_zero(tiles, cdiv(hp, SPLIT_TILE), stream);
+            for (int k = k0; k < k1; ++k) {
+                const int s = b[k];
+                const SetInfo &S = ctx->sets[set_ids[s]];
+                const StateView st = make_view(state[s], layout_of(ctx, S.H));
+                ListLaunch l{};
+                l.H = S.H;
+                l.hdr = st.hdr;
+                l.cstart = ws_cstart + W.cell_base[k];
+                for (int a = 0; a < 3; ++a) l.kp[a] = st.pos[a];
+                l.r = st.r;
+                l.cand = st.cand;
+                l.dec = st.dec;
+                l.k2 = p.k * p.k;
+                l.heavy_cost = (uint32_t)p.heavy_cost;
+                l.set_slot = (uint32_t)k;
+                l.q_base = W.q_off[k] - q0;
+                l.flag = flag + W.q_off[k];
+                l.ids = ids + W.q_off[k];
+                l.tile_heavy = tiles;
+                launch_cost(l, stream);
+            }
+            uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy) + q0;
+            uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light) + q0;
+            uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts) + 4 * ph_i;
+            launch_split(flag + q0, ids + q0, hp, (uint32_t)p.heavy_cost, tiles, heavy, light,
+                         reinterpret_cast<uint32_t *>(w + W.lcost) + q0, counts, ws_pay + W.n_total * rec, stream);
+            if (ph_i == 0) launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
+            BatchArgs a{};
+            a.desc = table;
+            a.pay = ws_pay;
+            a.pstride = (uint32_t)W.pstride;
+            a.cstart = ws_cstart;
+            a.heavy = heavy;
+            a.light = light;
+            a.counts = counts;
+            a.k = p.k;
+            a.cos_min = p.normal_cos_min;
+            a.lanes_light = p.lanes_light;
+            a.lanes_heavy = p.lanes_heavy;
+            if (pe) HIP_TRY(hipEventRecord(pe->e[3], stream));
+            launch_gather(a, hp, nrm_test, vcm, channels(ctx), stream);
+            if (pe) HIP_TRY(hipEventRecord(pe->e[4], stream));
+        }
         launch_tally(table, ids, W.h_total, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[5], stream));
         HIP_TRY(hipGetLastError());

@@ -240,7 +240,7 @@ inline WsLayout make_ws_layout(int n_sets, const int64_t *n_photons, const int64
     const size_t hk = 4 * (size_t)(W.h_total + 1);
     W.flag = take(hk);
     W.ids = take(hk);
-    W.tiles = take(4 * (size_t)(cdiv(W.h_total + 1, SPLIT_TILE) + 1));
+    W.tiles = take(4 * (size_t)(cdiv(W.h_total + 1, SPLIT_TILE) + 3));   // two gather phases' tiles
     W.heavy = take(hk);
     W.light = take(hk);
     W.lcost = take(hk);
