@@ -447,24 +447,30 @@ __global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *
 
 // inv[original index] = sorted position
 // Reads the input photons in their own order (coalesced) and writes each one's record, `rec` float4s,
-// at its sorted position: one contiguous 32- or 48-byte store region per photon.
+// at its sorted position. The record is written by `rec` neighbouring lanes, one float4 each, so one
+// store instruction of a wavefront writes 16 whole records (16 contiguous regions) rather than one
+// float4 of 64 records at 64 scattered places.
 __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *recs,
                                                       int rec)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t >> 2;                   // the photon
+    const int part = (int)(t & 3);              // which float4 of its record
+    if (j >= n || part >= rec) return;
     const uint32_t q = inv[j];
-    const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
-    const float dvcm = src.mis[0] ? src.mis[0][j] : 0.0f;
-    float4 *r = recs + (int64_t)q * rec;
-    r[0] = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
-    r[1] = make_float4(R, G, B, dvcm);
-    // the (normal, dVM) entry exists only where a normal test or vertex merging reads it
-    if (rec == 3) {
+    float4 v;
+    if (part == 0) {
+        const float R = src.flux[0][j], G = src.flux[1][j], B = src.flux[2][j];
+        v = make_float4(src.pos[0][j], src.pos[1][j], src.pos[2][j], luminance(R, G, B));
+    } else if (part == 1) {
+        v = make_float4(src.flux[0][j], src.flux[1][j], src.flux[2][j], src.mis[0] ? src.mis[0][j] : 0.0f);
+    } else {
+        // the (normal, dVM) entry exists only where a normal test or vertex merging reads it
         const float dvm = src.mis[0] ? src.mis[2][j] : 0.0f;
-        r[2] = src.nrm[0] ? make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm)
-                          : make_float4(0.0f, 0.0f, 1.0f, dvm);
+        v = src.nrm[0] ? make_float4(src.nrm[0][j], src.nrm[1][j], src.nrm[2][j], dvm)
+                       : make_float4(0.0f, 0.0f, 1.0f, dvm);
     }
+    recs[(int64_t)q * rec + part] = v;
 }
 
 // Four counters per thread: one 16-byte store when all four are live and the array is 16-byte
@@ -520,7 +526,7 @@ void build_grid(const GridLaunch &g, hipStream_t s)
                                                                       (int)cdiv(n, RS_CHUNK), nblk);
         uint32_t *ks, *inv;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true, true);
-        permute_kernel<<<nb, 256, 0, s>>>(g.src, n, inv, g.pay + g.pay_off * g.rec, g.rec);
+        permute_kernel<<<(int)cdiv(4 * n, 256), 256, 0, s>>>(g.src, n, inv, g.pay + g.pay_off * g.rec, g.rec);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
     excl_scan(g.cstart, nc, g.part3, s, &g.hdr->ncells, 1);
