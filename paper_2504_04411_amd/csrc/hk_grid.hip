@@ -186,11 +186,13 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *key
 
 // Stable scatter, one wavefront per segment and no barrier between the block's waves. The counts
 // hist[d * nseg + seg], scanned as one array (digit-major), give each segment's first position for
-// digit d: all keys of smaller digits, then those of digit d in earlier segments. The wave keeps them
-// in its own LDS row; the chunk is visited in rounds of 64 consecutive
-// keys, a key's rank among the round's equal digits comes from eight ballots, and the first lane of
-// each digit then advances the row by the digit's count in the round (a wave's LDS accesses are
-// performed in order, so the next round reads the advanced value).
+// digit d: all keys of smaller digits, then those of digit d in earlier segments. The wave first
+// sorts its chunk locally: the chunk's digit counts and their scan give each digit's local start,
+// the chunk is visited in rounds of 64 consecutive keys, a key's rank among the round's equal
+// digits comes from eight ballots, and the first lane of each digit advances the digit's running
+// local position (a wave's LDS accesses are performed in order, so the next round reads the
+// advanced value). Keys and values are staged in LDS in that order and then written out in it:
+// neighbouring lanes mostly hold the same digit, so their global positions are neighbours too.
 // With `inv` (the last pass), the inverse permutation is written instead of the sorted values:
 // inv[source index] = sorted position.
 __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
@@ -198,16 +200,13 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
                                                                 int shift, const uint32_t *offs, int nseg,
                                                                 int nblk, uint32_t *inv)
 {
-    __shared__ uint32_t row[RS_WAVES][256];
+    __shared__ uint32_t gbase[RS_WAVES][256];       // global start of each digit minus its local start
+    __shared__ uint32_t lrow[RS_WAVES][256];        // counts, then the running local position per digit
+    __shared__ uint32_t sk[RS_WAVES][RS_CHUNK], sv[RS_WAVES][RS_CHUNK];
     const int blk = rs_block(nblk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int seg = blk * RS_WAVES + w;
     if (blk < 0 || seg >= nseg) return;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int d = 4 * lane + j;
-        row[w][d] = offs[(int64_t)d * nseg + seg];
-    }
     const int64_t base = (int64_t)seg * RS_CHUNK + lane;
     uint32_t k[RS_ITEMS], v[RS_ITEMS];
 #pragma unroll
@@ -215,6 +214,28 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
         const int64_t q = base + 64 * i;
         k[i] = q < n ? kin[q] : 0u;
         v[i] = vin ? (q < n ? vin[q] : 0u) : (uint32_t)q;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) lrow[w][4 * lane + j] = 0u;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i)
+        if (base + 64 * i < n) atomicAdd(&lrow[w][(k[i] >> shift) & 255u], 1u);
+    __builtin_amdgcn_wave_barrier();
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        c[j] = lrow[w][4 * lane + j];
+        sum += c[j];
+    }
+    uint32_t ex = wave_incl_scan(sum) - sum;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int d = 4 * lane + j;
+        lrow[w][d] = ex;
+        gbase[w][d] = offs[(int64_t)d * nseg + seg] - ex;
+        ex += c[j];
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __builtin_amdgcn_wave_barrier();
@@ -230,17 +251,29 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = __popcll(peers & lt);
-        const uint32_t pos = row[w][d] + rank;
+        const uint32_t pos = lrow[w][d] + rank;
         __builtin_amdgcn_wave_barrier();
         if (valid) {
-            kout[pos] = k[i];
-            if (inv)
-                inv[v[i]] = pos;
-            else
-                vout[pos] = v[i];
-            if (rank == 0) row[w][d] = pos + (uint32_t)__popcll(peers);
+            sk[w][pos] = k[i];
+            sv[w][pos] = v[i];
+            if (rank == 0) lrow[w][d] = pos + (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    const int64_t left = n - (int64_t)seg * RS_CHUNK;
+    const int nvalid = left < RS_CHUNK ? (int)left : RS_CHUNK;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int p = 64 * i + lane;
+        if (p < nvalid) {
+            const uint32_t key = sk[w][p], val = sv[w][p];
+            const uint32_t pos = gbase[w][(key >> shift) & 255u] + (uint32_t)p;
+            kout[pos] = key;
+            if (inv)
+                inv[val] = pos;
+            else
+                vout[pos] = val;
+        }
     }
 }
 
