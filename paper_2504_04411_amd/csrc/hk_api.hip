@@ -602,18 +602,28 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             HIP_TRY(hipEventRecord(ctx->gfork, stream));
             for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(ctx->gs[gi], ctx->gfork, 0));
         }
-        for (int k = 0; k < kb; ++k) {
-            const int gs = k % W.ngs;
-            grid_of(k, gs == 0 ? stream : ctx->gs[gs], gs);
-        }
+        // each phase's sets, largest first, go to the grid stream with the fewest light vertices so far
+        // (the second phase's to streams 1..)
+        int64_t load[GRID_STREAMS] = {};
+        auto spread = [&](int k0, int k1, int g0) {
+            std::vector<int> ord;
+            for (int k = k0; k < k1; ++k) ord.push_back(k);
+            std::stable_sort(ord.begin(), ord.end(),
+                             [&](int x, int y) { return ph[b[x]].n_stored > ph[b[y]].n_stored; });
+            for (int k : ord) {
+                int gs = g0;
+                for (int gi = g0 + 1; gi < W.ngs; ++gi)
+                    if (load[gi] < load[gs]) gs = gi;
+                load[gs] += ph[b[k]].n_stored + 1;
+                grid_of(k, gs == 0 ? stream : ctx->gs[gs], gs);
+            }
+        };
+        spread(0, kb, 0);
         for (int gi = 1; gi < W.ngs; ++gi) {
             HIP_TRY(hipEventRecord(ctx->gjoin[gi], ctx->gs[gi]));
             HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin[gi], 0));
         }
-        for (int k = kb; k < nb; ++k) {
-            const int gs = 1 + (k - kb) % (W.ngs - 1);
-            grid_of(k, ctx->gs[gs], gs);
-        }
+        spread(kb, nb, 1);
         if (kb < nb)
             for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipEventRecord(ctx->gjoin2[gi], ctx->gs[gi]));
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));

@@ -480,15 +480,17 @@ __global__ __launch_bounds__(RS_THREADS) void keys_hist_kernel(const SetHeader *
 
 // inv[original index] = sorted position
 // Reads the input photons in their own order (coalesced) and writes each one's record, `rec` float4s,
-// at its sorted position. The record is written by `rec` neighbouring lanes, one float4 each, so one
-// store instruction of a wavefront writes 16 whole records (16 contiguous regions) rather than one
-// float4 of 64 records at 64 scattered places.
+// at its sorted position. The record is written by neighbouring lanes, one float4 each (two lanes
+// per photon for two-float4 records, four for three), so one store instruction of a wavefront writes
+// 32 or 16 whole records (as many contiguous regions) rather than one float4 of 64 records at 64
+// scattered places.
 __global__ __launch_bounds__(256) void permute_kernel(PhotonSrc src, int64_t n, const uint32_t *inv, float4 *recs,
                                                       int rec)
 {
+    const int lg = rec == 2 ? 1 : 2;            // log2 of the lanes per photon
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t j = t >> 2;                   // the photon
-    const int part = (int)(t & 3);              // which float4 of its record
+    const int64_t j = t >> lg;                  // the photon
+    const int part = (int)(t & ((1 << lg) - 1));   // which float4 of its record
     if (j >= n || part >= rec) return;
     const uint32_t q = inv[j];
     float4 v;
@@ -559,7 +561,8 @@ void build_grid(const GridLaunch &g, hipStream_t s)
                                                                       (int)cdiv(n, RS_CHUNK), nblk);
         uint32_t *ks, *inv;
         radix_sort(g.keyA, g.valA, g.keyB, g.valB, n, 24, g.hist, g.part, s, &ks, &inv, true, true);
-        permute_kernel<<<(int)cdiv(4 * n, 256), 256, 0, s>>>(g.src, n, inv, g.pay + g.pay_off * g.rec, g.rec);
+        permute_kernel<<<(int)cdiv((g.rec == 2 ? 2 : 4) * n, 256), 256, 0, s>>>(g.src, n, inv,
+                                                                            g.pay + g.pay_off * g.rec, g.rec);
         cell_count_kernel<<<nb, 256, 0, s>>>(g.hdr, ks, n, g.cstart);
     }
     excl_scan(g.cstart, nc, g.part3, s, &g.hdr->ncells, 1);
