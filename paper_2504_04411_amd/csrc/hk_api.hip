@@ -542,14 +542,36 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         if (pe) HIP_TRY(hipEventRecord(pe->e[0], stream));
         uint32_t *ws_cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
         float4 *ws_pay = reinterpret_cast<float4 *>(w + W.pay);
-        // 1. per set: advance the iteration on the device and choose the cell size
+        // 0. the set table (state offsets, work-list and cell offsets) for every kernel of the batch
+        SetDesc desc[MAX_BATCH];
+        uint32_t Hk[MAX_BATCH];
+        double Jk[MAX_BATCH];
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
-            const StateView st = make_view(state[s], layout_of(ctx, S.H));
-            launch_plan(st.hdr, st.mprefix, (double)ph[s].J_emitted, p.cell_scale, p.cell_quantile, W.max_cells[k],
-                        stream);
+            const Layout L = layout_of(ctx, S.H);
+            SetDesc &d = desc[k];
+            memset(&d, 0, sizeof d);
+            d.state = static_cast<char *>(state[s]);
+            d.arr = L.arr;
+            d.stride = L.stride;
+            d.H = (uint32_t)S.H;
+            d.pay_off = W.pay_off[k];
+            d.cell_base = W.cell_base[k];
+            d.max_iters = (uint32_t)p.max_iters;
+            d.mprefix = L.mprefix;
+            d.fctab = L.fctab;
+            d.lbtab = L.lbtab;
+            d.hdr = L.hdr;
+            d.q_off = W.q_off[k];
+            d.max_cells = W.max_cells[k];
+            Hk[k] = (uint32_t)S.H;
+            Jk[k] = (double)ph[s].J_emitted;
         }
+        SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
+        launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
+        // 1. per set: advance the iteration on the device and choose the cell size (one launch)
+        launch_plan_batch(table, nb, Jk, p.cell_scale, p.cell_quantile, stream);
         // 2. critical values for the kept-iteration counts this iteration can reach, on the second
         //    stream: they need only the plan's iteration index and J sums, and run beside the grids
         HIP_TRY(hipEventRecord(ctx->fork, stream));
@@ -629,30 +651,10 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
         HIP_TRY(hipStreamWaitEvent(stream, ctx->join, 0));
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
-        // 4. per phase: the work list over the phase's sets, one gather / test / update launch; the
-        //    set table once before the first; then the radius histograms and pair counts of the batch
+        // 4. per phase: the work list over the phase's sets, one gather / test / update launch; then
+        //    the radius histograms and pair counts of the batch
         uint32_t *flag = reinterpret_cast<uint32_t *>(w + W.flag);
         uint32_t *ids = reinterpret_cast<uint32_t *>(w + W.ids);
-        SetDesc desc[MAX_BATCH];
-        for (int k = 0; k < nb; ++k) {
-            const int s = b[k];
-            const SetInfo &S = ctx->sets[set_ids[s]];
-            const Layout L = layout_of(ctx, S.H);
-            SetDesc &d = desc[k];
-            memset(&d, 0, sizeof d);
-            d.state = static_cast<char *>(state[s]);
-            d.arr = L.arr;
-            d.stride = L.stride;
-            d.H = (uint32_t)S.H;
-            d.pay_off = W.pay_off[k];
-            d.cell_base = W.cell_base[k];
-            d.max_iters = (uint32_t)p.max_iters;
-            d.mprefix = L.mprefix;
-            d.fctab = L.fctab;
-            d.lbtab = L.lbtab;
-            d.hdr = L.hdr;
-        }
-        SetDesc *table = reinterpret_cast<SetDesc *>(w + W.desc);
         for (int ph_i = 0; ph_i < 2; ++ph_i) {
             const int k0 = ph_i == 0 ? 0 : kb, k1 = ph_i == 0 ? kb : nb;
             if (k0 >= k1) continue;
@@ -674,33 +676,23 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             const int64_t hp = (k1 < nb ? (int64_t)W.q_off[k1] : W.h_total) - q0;   // the phase's entries
             uint32_t *tiles = reinterpret_cast<uint32_t *>(w + W.tiles) + (ph_i == 0 ? 0 : cdiv(q0, SPLIT_TILE) + 1);
             launch_zero(tiles, cdiv(hp, SPLIT_TILE), stream);
-            for (int k = k0; k < k1; ++k) {
-                const int s = b[k];
-                const SetInfo &S = ctx->sets[set_ids[s]];
-                const StateView st = make_view(state[s], layout_of(ctx, S.H));
-                ListLaunch l{};
-                l.H = S.H;
-                l.hdr = st.hdr;
-                l.cstart = ws_cstart + W.cell_base[k];
-                for (int a = 0; a < 3; ++a) l.kp[a] = st.pos[a];
-                l.r = st.r;
-                l.cand = st.cand;
-                l.dec = st.dec;
-                l.k2 = p.k * p.k;
-                l.heavy_cost = (uint32_t)p.heavy_cost;
-                l.set_slot = (uint32_t)k;
-                l.q_base = W.q_off[k] - q0;
-                l.flag = flag + W.q_off[k];
-                l.ids = ids + W.q_off[k];
-                l.tile_heavy = tiles;
-                launch_cost(l, stream);
-            }
+            CostBatch cb{};
+            cb.desc = table;
+            cb.k0 = k0;
+            cb.k1 = k1;
+            cb.q0 = q0;
+            cb.cstart = ws_cstart;
+            cb.flag = flag;
+            cb.ids = ids;
+            cb.tile_heavy = tiles;
+            cb.k2 = p.k * p.k;
+            cb.heavy_cost = (uint32_t)p.heavy_cost;
+            launch_cost_batch(cb, Hk, stream);
             uint32_t *heavy = reinterpret_cast<uint32_t *>(w + W.heavy) + q0;
             uint32_t *light = reinterpret_cast<uint32_t *>(w + W.light) + q0;
             uint32_t *counts = reinterpret_cast<uint32_t *>(w + W.counts) + 4 * ph_i;
             launch_split(flag + q0, ids + q0, hp, (uint32_t)p.heavy_cost, tiles, heavy, light,
                          reinterpret_cast<uint32_t *>(w + W.lcost) + q0, counts, ws_pay + W.n_total * rec, stream);
-            if (ph_i == 0) launch_upload(table, desc, sizeof(SetDesc) * nb, stream);
             BatchArgs a{};
             a.desc = table;
             a.pay = ws_pay;
@@ -717,7 +709,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
             launch_gather(a, hp, nrm_test, vcm, channels(ctx), stream);
             if (pe) HIP_TRY(hipEventRecord(pe->e[4], stream));
         }
-        launch_tally(table, ids, W.h_total, stream);
+        launch_tally(table, Hk, nb, stream);
         if (pe) HIP_TRY(hipEventRecord(pe->e[5], stream));
         HIP_TRY(hipGetLastError());
     }

@@ -521,9 +521,8 @@ void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int 
 // over the whole batch give the heavy list and the light list, both in set order.
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
+__device__ __forceinline__ void cost_items(const ListLaunch &l, int64_t q0)
 {
-    const int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool in = q0 < l.H;
     const int64_t q = in ? q0 : l.H - 1;
     const float p[3] = {l.kp[0][q], l.kp[1][q], l.kp[2][q]};
@@ -566,10 +565,46 @@ __global__ __launch_bounds__(256) void cost_kernel(ListLaunch l)
     }
 }
 
-void launch_cost(const ListLaunch &l, hipStream_t s)
+// One launch over the sets of a gather phase: block b serves 256 kernels of the set block_set picks.
+__global__ __launch_bounds__(256) void cost_batch_kernel(CostBatch c, SetBlocks B)
 {
-    if (l.H <= 0) return;
-    cost_kernel<<<(int)cdiv(l.H, 256), 256, 0, s>>>(l);
+    const int i = block_set(B, blockIdx.x);
+    const int k = c.k0 + i;
+    const SetDesc D = c.desc[k];
+    const char *arr = D.state + D.arr;
+    auto fs = [&](int slot) { return reinterpret_cast<const float *>(arr + (size_t)slot * D.stride); };
+    auto us = [&](int slot) { return reinterpret_cast<const uint32_t *>(arr + (size_t)slot * D.stride); };
+    ListLaunch l{};
+    l.H = D.H;
+    l.hdr = reinterpret_cast<SetHeader *>(D.state + D.hdr);
+    l.cstart = c.cstart + D.cell_base;
+    for (int a = 0; a < 3; ++a) l.kp[a] = fs(SL_POS + a);
+    l.r = fs(SL_R);
+    l.cand = us(SL_CAND);
+    l.dec = us(SL_DEC);
+    l.k2 = c.k2;
+    l.heavy_cost = c.heavy_cost;
+    l.set_slot = (uint32_t)k;
+    l.q_base = D.q_off - c.q0;
+    l.flag = c.flag + D.q_off;
+    l.ids = c.ids + D.q_off;
+    l.tile_heavy = c.tile_heavy;
+    cost_items(l, (int64_t)(blockIdx.x - B.pre[i]) * 256 + threadIdx.x);
+}
+
+void launch_cost_batch(const CostBatch &c, const uint32_t *H, hipStream_t s)
+{
+    SetBlocks B{};
+    B.n = c.k1 - c.k0;
+    if (B.n <= 0) return;
+    uint32_t nblk = 0;
+    for (int i = 0; i < B.n; ++i) {
+        B.pre[i] = nblk;
+        nblk += (uint32_t)cdiv(H[c.k0 + i], 256);
+    }
+    B.pre[B.n] = nblk;
+    if (nblk == 0) return;
+    cost_batch_kernel<<<(int)nblk, 256, 0, s>>>(c, B);
 }
 
 // Stable partition of the batch's work list, heavy kernels first, in kernel order within each list
@@ -687,47 +722,34 @@ void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost,
 
 // ------------------------------------------------------------------------------------------------
 // after the update: per set, the histogram of the new radii (the next plan's cell size) and the
-// in-disk pairs of the iteration. The work list's entries are in set order, so a block's range
-// belongs to one set except at set boundaries; the block tallies its first set in LDS and adds any
-// other set's entries directly.
+// in-disk pairs and candidate tests of the iteration. Every block serves TALLY_PER_BLOCK kernels of
+// one set, tallies them in LDS and adds its nonzero bins and totals to the set's header.
 // ------------------------------------------------------------------------------------------------
 
 constexpr int TALLY_PER_BLOCK = 4096;
 
-__global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const uint32_t *ids, int64_t n)
+__global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, SetBlocks B)
 {
     __shared__ uint32_t hist[RHIST_BINS];
     __shared__ unsigned long long pairs, cands;
-    const int64_t b0 = (int64_t)blockIdx.x * TALLY_PER_BLOCK;
-    const int64_t b1 = min(n, b0 + (int64_t)TALLY_PER_BLOCK);
-    const uint32_t set0 = ids[b0] >> Q_BITS;
-    const SetDesc D0 = desc[set0];
-    SetHeader *h0 = reinterpret_cast<SetHeader *>(D0.state + D0.hdr);
-    const float r1_0 = h0->r1;
+    const int k = block_set(B, blockIdx.x);
+    const SetDesc D = desc[k];
+    SetHeader *h = reinterpret_cast<SetHeader *>(D.state + D.hdr);
+    const float r1 = h->r1;
+    const char *arr = D.state + D.arr;
+    const float *rr = reinterpret_cast<const float *>(arr + (size_t)SL_R * D.stride);
+    const uint32_t *cnt = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D.stride);
+    const uint32_t *cand = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CAND * D.stride);
+    const int64_t q0 = (int64_t)(blockIdx.x - B.pre[k]) * TALLY_PER_BLOCK;
+    const int64_t q1 = min((int64_t)D.H, q0 + (int64_t)TALLY_PER_BLOCK);
     if (threadIdx.x < RHIST_BINS) hist[threadIdx.x] = 0u;
     if (threadIdx.x == 0) pairs = cands = 0ull;
     __syncthreads();
     unsigned long long acc = 0, accc = 0;
-    for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) {
-        const uint32_t id = ids[e];
-        const uint32_t set = id >> Q_BITS, q = id & ((1u << Q_BITS) - 1u);
-        if (set == set0) {
-            const char *arr = D0.state + D0.arr;
-            const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D0.stride)[q];
-            acc += reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D0.stride)[q];
-            accc += reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CAND * D0.stride)[q];
-            atomicAdd(&hist[radius_bin(r, r1_0)], 1u);
-        } else {
-            const SetDesc D = desc[set];
-            SetHeader *h = reinterpret_cast<SetHeader *>(D.state + D.hdr);
-            const char *arr = D.state + D.arr;
-            const float r = reinterpret_cast<const float *>(arr + (size_t)SL_R * D.stride)[q];
-            const uint32_t c = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CNT * D.stride)[q];
-            const uint32_t cc = reinterpret_cast<const uint32_t *>(arr + (size_t)SL_CAND * D.stride)[q];
-            atomicAdd(&h->rhist[radius_bin(r, h->r1)], 1u);
-            if (c) atomicAdd(&h->n_pairs, (unsigned long long)c);
-            if (cc) atomicAdd(&h->n_cand, (unsigned long long)cc);
-        }
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+        acc += cnt[q];
+        accc += cand[q];
+        atomicAdd(&hist[radius_bin(rr[q], r1)], 1u);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -737,15 +759,23 @@ __global__ __launch_bounds__(256) void tally_kernel(const SetDesc *desc, const u
     if ((threadIdx.x & (WAVE - 1)) == 0 && acc) atomicAdd(&pairs, acc);
     if ((threadIdx.x & (WAVE - 1)) == 0 && accc) atomicAdd(&cands, accc);
     __syncthreads();
-    if (threadIdx.x < RHIST_BINS && hist[threadIdx.x]) atomicAdd(&h0->rhist[threadIdx.x], hist[threadIdx.x]);
-    if (threadIdx.x == 0 && pairs) atomicAdd(&h0->n_pairs, pairs);
-    if (threadIdx.x == 0 && cands) atomicAdd(&h0->n_cand, cands);
+    if (threadIdx.x < RHIST_BINS && hist[threadIdx.x]) atomicAdd(&h->rhist[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 0 && pairs) atomicAdd(&h->n_pairs, pairs);
+    if (threadIdx.x == 0 && cands) atomicAdd(&h->n_cand, cands);
 }
 
-void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s)
+void launch_tally(const SetDesc *desc, const uint32_t *H, int nb, hipStream_t s)
 {
-    if (h_total <= 0) return;
-    tally_kernel<<<(int)cdiv(h_total, TALLY_PER_BLOCK), 256, 0, s>>>(desc, ids, h_total);
+    SetBlocks B{};
+    B.n = nb;
+    uint32_t nblk = 0;
+    for (int k = 0; k < nb; ++k) {
+        B.pre[k] = nblk;
+        nblk += (uint32_t)cdiv(H[k], TALLY_PER_BLOCK);
+    }
+    B.pre[nb] = nblk;
+    if (nblk == 0) return;
+    tally_kernel<<<(int)nblk, 256, 0, s>>>(desc, B);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -323,10 +323,9 @@ constexpr float CELL_XSUB = 4.0f;
 // from the top come from a suffix scan. Everything that changes between iterations lives in the
 // state, so a captured graph can replay the iteration.
 static_assert(RHIST_BINS == WAVE, "one lane per radius bin");
-__global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile,
-                            uint32_t max_cells)
+__device__ void plan_set(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile,
+                         uint32_t max_cells)
 {
-    if (blockIdx.x != 0) return;
     const int b = (int)threadIdx.x;
     uint64_t above = hdr->rhist[b];
 #pragma unroll
@@ -372,6 +371,20 @@ __global__ void plan_kernel(SetHeader *hdr, double *mprefix, double J, float cel
     }
     hdr->ncells = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2];
     hdr->cell = cell;
+}
+
+// One wavefront per set of a batch.
+struct PlanBatch {
+    const SetDesc *desc;
+    float cell_scale, quantile;
+    double J[MAX_BATCH];
+};
+
+__global__ __launch_bounds__(WAVE) void plan_batch_kernel(PlanBatch P)
+{
+    const SetDesc D = P.desc[blockIdx.x];
+    plan_set(reinterpret_cast<SetHeader *>(D.state + D.hdr), reinterpret_cast<double *>(D.state + D.mprefix),
+             P.J[blockIdx.x], P.cell_scale, P.quantile, D.max_cells);
 }
 
 // One thread: a grid of fixed cell size `cell` (grown until the cell count fits max_cells) over the
@@ -737,10 +750,15 @@ void init_set(const InitLaunch &g, hipStream_t s)
 }  // namespace hk
 
 namespace hk {
-void launch_plan(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile, uint32_t max_cells,
-                 hipStream_t s)
+void launch_plan_batch(const SetDesc *desc, int nb, const double *J, float cell_scale, float quantile,
+                       hipStream_t s)
 {
-    plan_kernel<<<1, 64, 0, s>>>(hdr, mprefix, J, cell_scale, quantile, max_cells);
+    PlanBatch P{};
+    P.desc = desc;
+    P.cell_scale = cell_scale;
+    P.quantile = quantile;
+    for (int k = 0; k < nb && k < MAX_BATCH; ++k) P.J[k] = J[k];
+    plan_batch_kernel<<<nb, WAVE, 0, s>>>(P);
 }
 // Small host tables (the set records of a batch, the radius lower bounds) travel to the device in
 // kernel arguments, UPLOAD_WORDS words per launch: the copy is ordered on the stream, needs no host

@@ -155,7 +155,30 @@ struct SetDesc {
     uint32_t cell_base;      // first cell start of the set in the combined cell-start array
     uint32_t max_iters;
     uint64_t mprefix, fctab, lbtab, hdr;   // byte offsets in the state
+    uint32_t q_off;          // first entry of the set in the batch's work list
+    uint32_t max_cells;      // cell-count bound of the set's grid plan
 };
+
+// Blocks of one launch over several sets of a batch (a kernel argument): the i-th set of the launch
+// owns blocks [pre[i], pre[i + 1]).
+struct SetBlocks {
+    int n;
+    uint32_t pre[MAX_BATCH + 1];
+};
+
+// The launch's set of block b: the largest i with pre[i] <= b (binary search over the argument).
+__device__ __forceinline__ int block_set(const SetBlocks &B, uint32_t b)
+{
+    int lo = 0, hi = B.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.pre[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;

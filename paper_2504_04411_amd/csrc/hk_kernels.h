@@ -141,19 +141,33 @@ void build_grid(const GridLaunch &g, hipStream_t s);
 void init_set(const InitLaunch &g, hipStream_t s);
 void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const uint32_t *dlen = nullptr,
                int extra = 0);
-void launch_plan(SetHeader *hdr, double *mprefix, double J, float cell_scale, float quantile, uint32_t max_cells,
-                 hipStream_t s);
+// Per iteration, one block per set of a batch (the set table must be on the device): advance the
+// iteration, append J, plan the grid.
+void launch_plan_batch(const SetDesc *desc, int nb, const double *J, float cell_scale, float quantile,
+                       hipStream_t s);
 void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream_t s);
 void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all, double alpha_f,
                   hipStream_t s);
-void launch_cost(const ListLaunch &l, hipStream_t s);
+// Expected cost of every kernel of sets k0 .. k1-1 of a batch (one gather phase, whose work list
+// starts at entry q0): flags, entries and the heavy counts per tile.
+struct CostBatch {
+    const SetDesc *desc;
+    int k0, k1;
+    uint32_t q0;
+    const uint32_t *cstart;      // the batch's cell starts
+    uint32_t *flag, *ids;        // the batch's work-list arrays
+    uint32_t *tile_heavy;        // the phase's heavy counts per tile (zeroed before)
+    float k2;
+    uint32_t heavy_cost;
+};
+void launch_cost_batch(const CostBatch &c, const uint32_t *H, hipStream_t s);   // H: hit points per batch slot
 void launch_split(uint32_t *cost, uint32_t *ids, int64_t n, uint32_t heavy_cost, const uint32_t *tile_heavy,
                   uint32_t *heavy, uint32_t *light, uint32_t *lcost, uint32_t *counts, float4 *sentinel,
                   hipStream_t s);
 void launch_zero(uint32_t *p, int64_t n, hipStream_t s);
 void launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);   // bytes: multiple of 4
 void launch_gather(const BatchArgs &a, int64_t h_total, bool nrm, bool vcm, int nch, hipStream_t s);
-void launch_tally(const SetDesc *desc, const uint32_t *ids, int64_t h_total, hipStream_t s);
+void launch_tally(const SetDesc *desc, const uint32_t *H, int nb, hipStream_t s);   // H: hit points per set
 
 // light-vertex generation for the box scene (one thread per slot)
 struct EmitLaunch {
