@@ -576,14 +576,14 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         //    stream: they need only the plan's iteration index and J sums, and run beside the grids
         HIP_TRY(hipEventRecord(ctx->fork, stream));
         HIP_TRY(hipStreamWaitEvent(ctx->aux, ctx->fork, 0));
+        uint8_t all[MAX_BATCH];
         for (int k = 0; k < nb; ++k) {
             const int s = b[k];
             const SetInfo &S = ctx->sets[set_ids[s]];
-            const StateView st = make_view(state[s], layout_of(ctx, S.H));
-            const bool all = all_in ? all_in[s] != 0 : fcrit_all(S, ph[s].J_emitted);
-            if (all_out) (*all_out)[s] = all ? 1 : 0;
-            launch_fcrit(st.hdr, st.fctab, st.mprefix, p.max_iters, all, p.alpha_f, ctx->aux);
+            all[k] = (all_in ? all_in[s] != 0 : fcrit_all(S, ph[s].J_emitted)) ? 1 : 0;
+            if (all_out) (*all_out)[s] = all[k];
         }
+        launch_fcrit(table, nb, all, p.max_iters, p.alpha_f, ctx->aux);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(ctx->join, ctx->aux));
         // 3. per set: sort the photons into the grid; the sets' builds are independent and run on

@@ -785,21 +785,39 @@ void launch_tally(const SetDesc *desc, const uint32_t *H, int nb, hipStream_t s)
 // some point); otherwise only t = iter is new, since with a constant J the earlier entries hold.
 // ------------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(64) void fcrit_kernel(const SetHeader *hdr, double *fctab, const double *mprefix,
-                                                   int all, double alpha)
+// One launch for a batch: blockIdx.y is the set, blockIdx.x the block of t values (all[k]) or 0.
+struct FcritBatch {
+    const SetDesc *desc;
+    double alpha;
+    uint8_t all[MAX_BATCH];
+};
+
+__global__ __launch_bounds__(64) void fcrit_kernel(FcritBatch F)
 {
+    const SetDesc D = F.desc[blockIdx.y];
+    const SetHeader *hdr = reinterpret_cast<const SetHeader *>(D.state + D.hdr);
+    double *fctab = reinterpret_cast<double *>(D.state + D.fctab);
+    const double *mprefix = reinterpret_cast<const double *>(D.state + D.mprefix);
+    const int all = F.all[blockIdx.y];
     const int iter = hdr->iter;
     const int t = all ? 1 + (int)(blockIdx.x * 64 + threadIdx.x) : iter;
     if (t > iter || (!all && (blockIdx.x != 0 || threadIdx.x != 0))) return;
     const double m = mprefix[iter] - mprefix[iter - t];
-    fctab[t] = (m >= 2.0) ? f_quantile((double)(NG - 1), (double)NG * (m - 1.0), alpha) : (double)NAN;
+    fctab[t] = (m >= 2.0) ? f_quantile((double)(NG - 1), (double)NG * (m - 1.0), F.alpha) : (double)NAN;
 }
 
-void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all,
-                  double alpha_f, hipStream_t s)
+void launch_fcrit(const SetDesc *desc, int nb, const uint8_t *all, int max_iters, double alpha_f, hipStream_t s)
 {
-    const int nb = all ? (int)cdiv(max_iters, 64) : 1;
-    fcrit_kernel<<<nb, 64, 0, s>>>(hdr, fctab, mprefix, all ? 1 : 0, alpha_f);
+    FcritBatch F{};
+    F.desc = desc;
+    F.alpha = alpha_f;
+    bool any_all = false;
+    for (int k = 0; k < nb && k < MAX_BATCH; ++k) {
+        F.all[k] = all[k];
+        any_all = any_all || all[k];
+    }
+    const int nx = any_all ? (int)cdiv(max_iters, 64) : 1;
+    fcrit_kernel<<<dim3(nx, nb), 64, 0, s>>>(F);
 }
 
 }  // namespace hk

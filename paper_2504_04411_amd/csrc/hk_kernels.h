@@ -146,8 +146,9 @@ void excl_scan(uint32_t *d, int64_t len, uint32_t *part, hipStream_t s, const ui
 void launch_plan_batch(const SetDesc *desc, int nb, const double *J, float cell_scale, float quantile,
                        hipStream_t s);
 void launch_plan_fixed(SetHeader *hdr, float cell, uint32_t max_cells, hipStream_t s);
-void launch_fcrit(const SetHeader *hdr, double *fctab, const double *mprefix, int max_iters, bool all, double alpha_f,
-                  hipStream_t s);
+// Critical values of a batch's sets in one launch (the set table on the device); all[k]: recompute
+// every kept-iteration count of set k, else only the new one.
+void launch_fcrit(const SetDesc *desc, int nb, const uint8_t *all, int max_iters, double alpha_f, hipStream_t s);
 // Expected cost of every kernel of sets k0 .. k1-1 of a batch (one gather phase, whose work list
 // starts at entry q0): flags, entries and the heavy counts per tile.
 struct CostBatch {
