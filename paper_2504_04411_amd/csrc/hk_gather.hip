@@ -318,6 +318,7 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
     }
     const uint32_t t_new = t_prev + 1u;
     const double m = active ? mprefix[iter] - mprefix[iter - (int)t_new] : 2.0;
+    const double inv_m = 1.0 / m;                 // one float64 division per lane, products after it
     const bool lead = active && j == 0;
     const double Fc = lead ? fctab[t_new] : 0.0;
     const uint32_t seen_prev = lead ? uslot(SL_NSEEN)[q] : 0u;
@@ -384,15 +385,15 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
             if (col < COLS && col / NG == ch) {
-                const double d = sg[k] - tl[ch] / NG;
+                const double d = sg[k] - tl[ch] * (1.0 / NG);
                 bl[ch] += d * d;
-                wl[ch] += qg[k] - sg[k] * sg[k] / m;
+                wl[ch] += qg[k] - sg[k] * sg[k] * inv_m;
             }
         }
     }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        ssb[ch] = group_sum<G>(bl[ch]) / m;
+        ssb[ch] = group_sum<G>(bl[ch]) * inv_m;
         ssw[ch] = group_sum<G>(wl[ch]);
     }
     const float flR = (float)fR, flG = (float)fG, flB = (float)fB;
@@ -404,7 +405,8 @@ __device__ __forceinline__ void process(const BatchArgs &A, Lds<CH> &L, uint32_t
         double F = (double)NAN;
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
-            const double Fch = (ssb[ch] / (NG - 1)) / (ssw[ch] / (NG * (m - 1.0)));
+            // (ssb / (NG - 1)) / (ssw / (NG (m - 1))) with one division
+            const double Fch = (ssb[ch] * (NG * (m - 1.0))) / ((double)(NG - 1) * ssw[ch]);
             if (seen > 0u && ssw[ch] > 0.0 && m >= 2.0 && Fch > Fc) shrink = 1;
             F = fmax(F, Fch);
         }
