@@ -184,8 +184,10 @@ def run_leg(name, args, pool):
     alu = ops / gather_s / 1e12
     J = sum(b.J for b in batches[0])
     wl = WORKLOADS[name]
-    bytes_launch = J * wl["P_b"] + H * (wl["G_h"] + STATE_RW)
-    gbps = bytes_launch * prof["launches"] / K / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else 0.0
+    # the iteration's algorithmic bytes, shared by its gather launches (one per batch of sets)
+    per_it = max(prof["launches"], 1) / K
+    bytes_launch = (J * wl["P_b"] + H * (wl["G_h"] + STATE_RW)) / per_it
+    gbps = bytes_launch / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else 0.0
     nrm = ws[0].kernels.nrm is not None
     vcm = p.mode == "vcm"
     kname = (f"gather_update_kernel<{str(nrm).lower()},{str(vcm).lower()},1,{tuning['lanes_light']},"
