@@ -151,7 +151,11 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
     }
     if (NRM && !ok) psi = wR = wG = wB = pR = pG = pB = 0.0f;
     if (CH == 1) {
+        // the slot's read is issued first and the flux sums, which do not depend on it, fill its latency
         double2 sv = L.slot[g][lane];
+        c.fR += (double)wR;
+        c.fG += (double)wG;
+        c.fB += (double)wB;
         const double x = (double)psi;
         sv.x += x;
         sv.y = fma(x, x, sv.y);
@@ -167,10 +171,10 @@ __device__ __forceinline__ void accumulate(const Cand &P, const Query &K, float 
             sv.y = fma(x, x, sv.y);
             L.slot[ch * NG + g][lane] = sv;
         }
+        c.fR += (double)wR;
+        c.fG += (double)wG;
+        c.fB += (double)wB;
     }
-    c.fR += (double)wR;
-    c.fG += (double)wG;
-    c.fB += (double)wB;
     c.cnt += ok ? 1u : 0u;
 }
 
