@@ -155,6 +155,48 @@ def test_graph_replay_matches_eager(mode):
     g.close()
 
 
+def test_two_gather_phases_graph_and_eager():
+    """Eight planar sets at 0.3 of the 16-set workload's sizes (5.9M light vertices, 370k hit points):
+    large enough that the batch is gathered in two phases (the second phase's grids built while the
+    first gather runs), checked by the launch count. A captured graph is replayed three times against
+    eager calls on a twin state, bit for bit, and 128 sampled kernels of every set of the eager
+    state against the oracle."""
+    G, GP, DP = _mods()
+    ws = G.config2(seed=2, n_sets=8, n_iter=3, scale=0.3)
+    eager = GP.make_estimator(ws[0])
+    graph = GP.make_estimator(ws[0])
+    for s, w in enumerate(ws):
+        _add_set(eager, s, w)
+        _add_set(graph, s, w)
+    ids = list(range(len(ws)))
+    rng = np.random.default_rng(21)
+    trackers = [GP.Tracker(w, np.sort(rng.choice(w.kernels.n, min(128, w.kernels.n), replace=False)),
+                           name=f"set{s}") for s, w in enumerate(ws)]
+    bufs = [DP.upload(w.photons(0)) for w in ws]
+    g = graph.capture(ids, bufs)
+    torch.cuda.synchronize()
+    eager.profile(True)
+    for it in range(3):
+        phs_host = [w.photons(it) for w in ws]
+        phs = [DP.upload(ph) for ph in phs_host]
+        for b, ph in zip(bufs, phs):
+            b.pos.copy_(ph.pos)
+            b.flux.copy_(ph.flux)
+        g.launch()
+        eager.iterate(ids, phs)
+        torch.cuda.synchronize()
+        for s in ids:
+            _same(_snapshot(graph, s), _snapshot(eager, s), f"replay {it + 1} set {s}")
+            trackers[s].step(eager, s, phs_host[s])
+    prof = eager.profile_read()
+    eager.profile(False)
+    print(f"  gather launches over 3 iterations: {prof['launches']}", flush=True)
+    assert prof["launches"] == 6, "the batch was expected to be gathered in two phases"
+    for s in ids:
+        trackers[s].finish(eager, s)
+    g.close()
+
+
 def test_graph_refuses_stale_sets():
     """A graph whose set was re-initialised, or that reached max_iters, is refused on the host."""
     G, GP, DP = _mods()
