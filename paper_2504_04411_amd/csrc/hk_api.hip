@@ -587,9 +587,9 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(ctx->join, ctx->aux));
         // 3. per set: sort the photons into the grid; the sets' builds are independent and run on
-        //    W.ngs streams at once. The first phase's sets (k < kb) use every grid stream (set k on
-        //    stream k mod ngs, stream 0 the caller's) and are joined before the first gather; the
-        //    second phase's sets follow on streams 1.. and are built while the first gather runs.
+        //    W.ngs streams at once. The first phase's sets (k < kb) use every grid stream (stream 0 is
+        //    the caller's) and are joined before the first gather; the second phase's sets follow on
+        //    streams 1.. and are built while the first gather runs.
         const int kb = phase_split(ctx, b, set_ids, ph, W.ngs);
         auto grid_of = [&](int k, hipStream_t gstream, int gs) {
             const int s = b[k];
