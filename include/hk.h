@@ -146,12 +146,12 @@ int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, c
 
 /* Runs one iteration (steps 1-6 above) for each of the n_sets (1..256, distinct) sets; ph[s] holds
  * set s's light vertices, state[s] its state, set_ids[s] its id. Each set's grid is built by its own
- * launches; the gather, test and update of up to 64 sets (about 2^27 stored light vertices in total,
- * about 89.4M with the normal test or vertex merging, whose payload records are 48 bytes)
+ * launches; the gather, test and update of up to 64 sets (at most 2^27 - 65 stored light vertices in
+ * total, 89,478,421 with the normal test or vertex merging, whose payload records are 48 bytes)
  * run as ONE launch over a work list spanning those sets, so many small, uneven sets fill the GPU
  * together. Sets with and without the normal test go to separate launches. `workspace` (device,
  * workspace_bytes long) must hold hk_workspace_bytes_batch over the sets (HK_E_SMALL_BUFFER
- * otherwise); a set holds at most 2^27 - 3 stored light vertices per iteration, 89,478,483 with the
+ * otherwise); a set holds at most 2^27 - 65 stored light vertices per iteration, 89,478,421 with the
  * normal test or vertex merging (HK_E_UNSUPPORTED).
  * Arguments of all sets are checked before any work is enqueued. Non-finite photon values are not
  * rejected: a NaN position never lands in a disk, a NaN flux makes that kernel's F NaN, which keeps

@@ -189,9 +189,10 @@ constexpr int SPLIT_TILE = 4096;                   // work-list entries per part
 // normal test or vertex merging reads it, (nx, ny, nz, dVM): 32 or 48 bytes
 constexpr int PAY_VEC = 3;
 __host__ __device__ constexpr int pay_rec(bool nrm_or_vcm) { return nrm_or_vcm ? 3 : 2; }
-// photons of one gather launch: the byte offsets of its records (and of the point at infinity after
-// them) fit 32 bits
-constexpr int64_t max_batch_photons(int rec) { return (int64_t)(0xFFFFFFFFull / (16ull * rec)) - 2; }
+// photons of one gather launch: the byte offsets of its records fit 32 bits, and so does every cursor
+// value a lane forms: a lane's cursor steps G records at a time and may pass the end of the last row
+// by up to 63 records before it moves to the point at infinity, which follows the records
+constexpr int64_t max_batch_photons(int rec) { return (int64_t)(0xFFFFFFFFull / (16ull * rec)) - 64; }
 
 inline uint32_t max_cells_for(int64_t n_photons)
 {

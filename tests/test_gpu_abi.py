@@ -71,20 +71,22 @@ def test_small_workspace_is_refused():
 
 
 def test_too_many_stored_vertices_is_unsupported():
-    """2^27 stored light vertices in one set exceed the 32-bit byte offsets of the payload; the call is
-    refused before anything is enqueued (the pointers are never read)."""
+    """2^27 stored light vertices in one set, and 2^27 - 64 (one more than the largest set without
+    normals: its 32-byte records, and a cursor passing the last row by up to 63 records, must keep
+    32-bit byte offsets), are refused before anything is enqueued (the pointers are never read)."""
     hk, DevicePhotons, Estimator, G = _mods()
     w = G.small_config0(seed=1, n_side=4, J=100)
     est = Estimator(w.params.r1)
     est.set_kernels(0, w.kernels.pos)
     dummy = torch.empty(64, dtype=torch.float32, device="cuda")
     rows = [dummy.data_ptr()] * 3
-    n = 1 << 27
-    ph = hk.make_photons(n, n, rows, rows)
     ws = est._workspace(1 << 20)
-    code = _code(hk.hk_iterate, est.ctx, [0], [ph], [est.states[0].data_ptr()], ws.data_ptr(), ws.numel(),
-                 est.stream)
-    assert code == hk.HK_E_UNSUPPORTED
+    for n in (1 << 27, (1 << 27) - 64):
+        ph = hk.make_photons(n, n, rows, rows)
+        code = _code(hk.hk_iterate, est.ctx, [0], [ph], [est.states[0].data_ptr()], ws.data_ptr(), ws.numel(),
+                     est.stream)
+        assert code == hk.HK_E_UNSUPPORTED, n
+    n = 1 << 27
     ph = hk.make_photons(n - 2, n - 1, rows, rows)          # more stored than emitted
     code = _code(hk.hk_iterate, est.ctx, [0], [ph], [est.states[0].data_ptr()], ws.data_ptr(), ws.numel(),
                  est.stream)
