@@ -184,6 +184,11 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *key
     rs_count_store(cnt, hist, nseg, blk);
 }
 
+// Waves per scatter workgroup. One: a workgroup's 10 KB of LDS fits beside a CU's full load of
+// gather wavefronts (12 x 12.5 KB of the 160 KB), so a set's sort can progress while another phase's
+// gather runs; a four-wave workgroup's 40 KB waits for the gather to drain.
+constexpr int RS_SCATTER_WAVES = 1;
+
 // Stable scatter, one wavefront per segment and no barrier between the block's waves. The counts
 // hist[d * nseg + seg], scanned as one array (digit-major), give each segment's first position for
 // digit d: all keys of smaller digits, then those of digit d in earlier segments. The wave first
@@ -195,17 +200,17 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist_kernel(const uint32_t *key
 // neighbouring lanes mostly hold the same digit, so their global positions are neighbours too.
 // With `inv` (the last pass), the inverse permutation is written instead of the sorted values:
 // inv[source index] = sorted position.
-__global__ __launch_bounds__(RS_THREADS) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
-                                                                uint32_t *kout, uint32_t *vout, int64_t n,
-                                                                int shift, const uint32_t *offs, int nseg,
-                                                                int nblk, uint32_t *inv)
+template <int SW>
+__global__ __launch_bounds__(64 * SW) void rs_scatter_kernel(const uint32_t *kin, const uint32_t *vin,
+                                                             uint32_t *kout, uint32_t *vout, int64_t n, int shift,
+                                                             const uint32_t *offs, int nseg, uint32_t *inv)
 {
-    __shared__ uint32_t gbase[RS_WAVES][256];       // global start of each digit minus its local start
-    __shared__ uint32_t lrow[RS_WAVES][256];        // counts, then the running local position per digit
-    __shared__ uint32_t sk[RS_WAVES][RS_CHUNK], sv[RS_WAVES][RS_CHUNK];
-    const int blk = rs_block(nblk);
+    __shared__ uint32_t gbase[SW][256];             // global start of each digit minus its local start
+    __shared__ uint32_t lrow[SW][256];              // counts, then the running local position per digit
+    __shared__ uint32_t sk[SW][RS_CHUNK], sv[SW][RS_CHUNK];
+    const int blk = rs_block((nseg + SW - 1) / SW);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int seg = blk * RS_WAVES + w;
+    const int seg = blk * SW + w;
     if (blk < 0 || seg >= nseg) return;
     const int64_t base = (int64_t)seg * RS_CHUNK + lane;
     uint32_t k[RS_ITEMS], v[RS_ITEMS];
@@ -294,8 +299,9 @@ void radix_sort(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, int64_t 
         if (shift > 0 || !first_hist_done)
             rs_hist_kernel<<<grid, RS_THREADS, 0, s>>>(ki, n, shift, hist, nseg, nblk);
         excl_scan(hist, (int64_t)256 * nseg, part, s, nullptr, 0);
-        rs_scatter_kernel<<<grid, RS_THREADS, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nseg, nblk,
-                                                      (last && inverse) ? vo : nullptr);
+        rs_scatter_kernel<RS_SCATTER_WAVES><<<8 * rs_per_xcd((int)cdiv(nseg, RS_SCATTER_WAVES)),
+                                              64 * RS_SCATTER_WAVES, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nseg,
+                                                                             (last && inverse) ? vo : nullptr);
         uint32_t *kt = ki;
         ki = ko;
         ko = kt;
