@@ -202,8 +202,10 @@ inline uint32_t max_cells_for(int64_t n_photons)
 }
 
 // The grids of a batch's sets are built on up to GRID_STREAMS streams at once (the sets are
-// independent until the gather); each stream has its own sort scratch.
-constexpr int GRID_STREAMS = 4;
+// independent until the gather); each stream has its own sort scratch. Three: with the critical
+// values' stream that makes four streams, as many as HIP gives a process hardware queues by default;
+// a fourth grid stream shares a queue with another, whose work then runs behind its own.
+constexpr int GRID_STREAMS = 3;
 
 struct SortScratch {
     size_t keyA = 0, keyB = 0, valA = 0, valB = 0, hist = 0, part = 0, part3 = 0;
