@@ -640,11 +640,25 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
                 grid_of(k, gs == 0 ? stream : ctx->gs[gs], gs);
             }
         };
+        // The second phase's grids go to the grid streams once the first gather is queued: a wait on a
+        // grid stream's event can be held until that stream's later work completes, so work queued
+        // behind the first phase's grids would delay the first gather. Under stream capture they are
+        // queued first instead: a graph replay runs its nodes in its own order, and one whose first
+        // gather came before the second phase's grids ran those grids one after another behind it.
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(stream, &cap));
+        const bool grids_b_late = cap == hipStreamCaptureStatusNone;
+        auto grids_b = [&]() -> int {
+            spread(kb, nb, 1);
+            for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipEventRecord(ctx->gjoin2[gi], ctx->gs[gi]));
+            return HK_OK;
+        };
         spread(0, kb, 0);
         for (int gi = 1; gi < W.ngs; ++gi) {
             HIP_TRY(hipEventRecord(ctx->gjoin[gi], ctx->gs[gi]));
             HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin[gi], 0));
         }
+        if (kb < nb && !grids_b_late && (rc = grids_b()) != HK_OK) return rc;
         if (pe) HIP_TRY(hipEventRecord(pe->e[1], stream));
         HIP_TRY(hipStreamWaitEvent(stream, ctx->join, 0));
         if (pe) HIP_TRY(hipEventRecord(pe->e[2], stream));
@@ -655,13 +669,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         for (int ph_i = 0; ph_i < 2; ++ph_i) {
             const int k0 = ph_i == 0 ? 0 : kb, k1 = ph_i == 0 ? kb : nb;
             if (k0 >= k1) continue;
-            if (ph_i == 1) {
-                // the second phase's grids go to the grid streams only once the first gather is queued:
-                // a wait on a grid stream's event can be held until that stream's later work completes,
-                // so work queued behind the first phase's grids would delay the first gather
-                spread(kb, nb, 1);
-                for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipEventRecord(ctx->gjoin2[gi], ctx->gs[gi]));
-            }
+            if (ph_i == 1 && grids_b_late && (rc = grids_b()) != HK_OK) return rc;
             if (ph_i == 1) {
                 // the second phase: its own profile record from here (its grids' wait, list, gather)
                 if (pe) {
