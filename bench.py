@@ -172,7 +172,8 @@ def run_leg(name, args, pool):
         prof = est.profile_read()
         est.profile(False)
         st = [est.stats(s) for s in ids]
-        reps.append(dict(dt=dt, prof=prof, pairs=sum(x["pairs"] for x in st), cand=sum(x["candidates"] for x in st)))
+        reps.append(dict(dt=dt, prof=prof, pairs=sum(x["pairs"] for x in st), cand=sum(x["candidates"] for x in st),
+                         pairs_set=[x["pairs"] for x in st]))
     order = sorted(range(R), key=lambda i: reps[i]["dt"])
     med = reps[order[R // 2]]
     radii = np.concatenate([est.radii(s).cpu().numpy() for s in ids])
@@ -200,6 +201,23 @@ def run_leg(name, args, pool):
                 "frac": round(gbps / HBM_PEAK_GBPS, 4),
                 "work_model": f"{wl['P_b']} B per light vertex + ({wl['G_h']} + {STATE_RW}) B per hit point per launch",
                 "algorithmic_bytes_per_launch": int(bytes_launch)}
+    # the two gather launches of a batch of several sets, each with its own sets' work: the first runs
+    # beside the second phase's grid builds, the second alone
+    phase_of = est.gather_phases(ids, batches[0])
+    by_phase = []
+    for ph_i in (0, 1):
+        n_l = prof["launches_phase"][ph_i]
+        if n_l == 0 or prof["launches_phase"][1] == 0:
+            continue
+        sel = [s for s in ids if phase_of[s] == ph_i]
+        h_p = sum(ws[s].kernels.n for s in sel)
+        ops_p = OPS_PER_QUERY * h_p * K + OPS_PER_PAIR * sum(med["pairs_set"][s] for s in sel)
+        t_p = prof["gather_ms_phase"][ph_i] / 1e3
+        by_phase.append({"phase": ph_i + 1, "sets": len(sel), "hit_points": h_p, "launches": n_l,
+                         "avg_launch_ms": round(prof["gather_ms_phase"][ph_i] / n_l, 4),
+                         "alu_achieved": round(ops_p / t_p / 1e12, 3),
+                         "alu_frac": round(ops_p / t_p / 1e12 / VALU_PEAK_TOPS, 4),
+                         "runs_beside": "the second phase's grid builds" if ph_i == 0 else "nothing"})
     out = {
         "workload": label, "hit_points": H, "light_paths_per_iteration": int(J), "iterations": K,
         "queries_per_s": round(H * K / med["dt"], 1), "ms_per_step": round(med["dt"] / K * 1e3, 4),
@@ -217,6 +235,8 @@ def run_leg(name, args, pool):
         "dominant_kernel": {"kernel": kname, "avg_launch_ms": round(launch_ms, 4), "launches": int(prof["launches"])},
         "alu_roofline": alu_roof, "hbm_roofline": hbm_roof, "traffic": traffic,
     }
+    if by_phase:
+        out["gather_launches_by_phase"] = by_phase
     est.close()
     del batches
     torch.cuda.synchronize()

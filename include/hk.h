@@ -339,9 +339,17 @@ double hk_f_quantile(double d1, double d2, double alpha);
  * [1] wait for the critical values beyond the grid builds (they run on a second stream beside them),
  * [2] work lists and set table, [3] the gather / test / update launches alone, [4] radius histogram
  * and pair tally; then [5] the number of gather launches timed (two per batch of two or more sets:
- * the second phase's grids are built while the first phase's gather runs). */
+ * the second phase's grids are built while the first phase's gather runs); then [6], [7] the
+ * gather launches' milliseconds of first and of second phases, [8], [9] their numbers. */
 int hk_profile_enable(hk_ctx *ctx, int on);
 int hk_profile_read(hk_ctx *ctx, double *out, int n);
+
+/* Which gather phase (0: first, 1: second) each of the n_sets sets would take in an hk_iterate call
+ * with the same set_ids and light vertices (ph[s].n_stored is read, and whether ph[s].nrm[0] is NULL;
+ * no pointer is dereferenced): phase[s] for set_ids[s]. Host-side, nothing is enqueued. Sets must have kernels
+ * (HK_E_BAD_STATE); bad arguments give HK_E_INVALID_ARG. Used to attribute work to the two gather
+ * launches of a batch when timing them. */
+int hk_gather_phases(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, int *phase);
 
 int hk_version(void);
 const char *hk_last_error(void);

@@ -57,6 +57,7 @@ struct SetInfo {
 constexpr int PROF_EVENTS = 6;   // start, grids, critical values joined, list, gather, tally
 struct ProfEv {
     hipEvent_t e[PROF_EVENTS];
+    int phase = 0;                      // gather phase of the batch this record times
 };
 
 }  // namespace
@@ -397,9 +398,9 @@ static int validate(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photon
         if (P.J_emitted > (uint64_t)1 << 52) return fail(HK_E_INVALID_ARG, "J_emitted too large");
         const int64_t lim = max_batch_photons(pay_rec(nrm_test_of(ctx, id, P) || vcm));
         if (P.n_stored > MAX_STORED || P.n_stored > lim)
-            return fail(HK_E_UNSUPPORTED, "set %d: at most %lld stored light vertices per set (%s)", id,
-                        (long long)(lim < MAX_STORED ? lim : MAX_STORED),
-                        lim < MAX_STORED ? "48-byte records with the normal test or merging" : "2^27 - 1");
+            return fail(HK_E_UNSUPPORTED, "set %d: at most %lld stored light vertices per set with %d-byte payload records",
+                        id, (long long)(lim < MAX_STORED ? lim : MAX_STORED),
+                        16 * pay_rec(nrm_test_of(ctx, id, P) || vcm));
         if (P.n_stored > 0) {
             for (int a = 0; a < 3; ++a)
                 if (!P.pos[a] || !P.flux[a]) return fail(HK_E_INVALID_ARG, "set %d: pos/flux is NULL", id);
@@ -539,6 +540,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
         const int rec = pay_rec(nrm_test || vcm);          // float4s per payload record
         ProfEv *pe = prof ? prof_slot(ctx) : nullptr;
         if (prof && !pe) return fail(HK_E_HIP, "hipEventCreate failed");
+        if (pe) pe->phase = 0;
         if (pe) HIP_TRY(hipEventRecord(pe->e[0], stream));
         uint32_t *ws_cstart = reinterpret_cast<uint32_t *>(w + W.cstart);
         float4 *ws_pay = reinterpret_cast<float4 *>(w + W.pay);
@@ -676,6 +678,7 @@ static int enqueue(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons
                     HIP_TRY(hipEventRecord(pe->e[5], stream));
                     pe = prof_slot(ctx);
                     if (!pe) return fail(HK_E_HIP, "hipEventCreate failed");
+                    pe->phase = 1;
                     HIP_TRY(hipEventRecord(pe->e[0], stream));
                 }
                 for (int gi = 1; gi < W.ngs; ++gi) HIP_TRY(hipStreamWaitEvent(stream, ctx->gjoin2[gi], 0));
@@ -1394,20 +1397,44 @@ extern "C" int hk_profile_enable(hk_ctx *ctx, int on)
     return HK_OK;
 }
 
+extern "C" int hk_gather_phases(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, int *phase)
+{
+    if (!ctx || !phase) return fail(HK_E_INVALID_ARG, "bad arguments");
+    if (n_sets < 1 || n_sets > MAX_SETS || !set_ids || !ph)
+        return fail(HK_E_INVALID_ARG, "bad set arguments (n_sets in [1, %d], arrays non-NULL)", MAX_SETS);
+    for (int s = 0; s < n_sets; ++s) {
+        const int id = set_ids[s];
+        if (id < 0 || id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", id);
+        if (!ctx->sets[id].init) return fail(HK_E_BAD_STATE, "set %d has no kernels (call hk_set_kernels)", id);
+        if (ph[s].n_stored < 0) return fail(HK_E_INVALID_ARG, "set %d: n_stored < 0", id);
+    }
+    for (const auto &b : make_batches(ctx, n_sets, set_ids, ph)) {
+        const int nb = (int)b.size();
+        const int ngs = nb < GRID_STREAMS ? nb : GRID_STREAMS;
+        const int kb = phase_split(ctx, b, set_ids, ph, ngs);
+        for (int k = 0; k < nb; ++k) phase[b[k]] = k < kb ? 0 : 1;
+    }
+    return HK_OK;
+}
+
 extern "C" int hk_profile_read(hk_ctx *ctx, double *out, int n)
 {
     if (!ctx || !out || n < 0) return fail(HK_E_INVALID_ARG, "bad arguments");
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->ev_used.empty()) HIP_TRY(hipEventSynchronize(ctx->ev_used.back().e[PROF_EVENTS - 1]));
-    double acc[PROF_EVENTS] = {};   // phase totals, then the number of batches
+    // step totals, the number of gather launches, then per gather phase (first, second) the launches'
+    // time and their number
+    double acc[PROF_EVENTS + 4] = {};
     for (auto &pe : ctx->ev_used) {
         float ms;
         for (int k = 0; k + 1 < PROF_EVENTS; ++k) {
             HIP_TRY(hipEventElapsedTime(&ms, pe.e[k], pe.e[k + 1]));
             acc[k] += ms;
+            if (k == 3) acc[PROF_EVENTS + (pe.phase ? 1 : 0)] += ms;
         }
         acc[PROF_EVENTS - 1] += 1.0;
+        acc[PROF_EVENTS + 2 + (pe.phase ? 1 : 0)] += 1.0;
     }
-    for (int k = 0; k < n && k < PROF_EVENTS; ++k) out[k] = acc[k];
+    for (int k = 0; k < n && k < PROF_EVENTS + 4; ++k) out[k] = acc[k];
     return HK_OK;
 }

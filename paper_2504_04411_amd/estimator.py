@@ -121,6 +121,11 @@ class Estimator:
         hk.hk_iterate(self.ctx, list(set_ids), [p.struct() for p in photons],
                       [self.states[s].data_ptr() for s in set_ids], ws.data_ptr(), ws.numel(), self.stream)
 
+    def gather_phases(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]) -> list:
+        """Gather phase (0 or 1) of every set within its batch, as an iterate call with these sets
+        and light vertices would run them (host-side; nothing is enqueued)."""
+        return hk.hk_gather_phases(self.ctx, list(set_ids), [p.struct() for p in photons])
+
     def capture(self, set_ids: Sequence[int], photons: Sequence[DevicePhotons]) -> "Graph":
         """Captures one iteration of the sets into a graph; refill `photons` in place between launches."""
         wsb = self.workspace_for(photons, set_ids)
@@ -220,7 +225,7 @@ class Estimator:
     def profile_read(self) -> dict:
         v = hk.hk_profile_read(self.ctx)
         return dict(grid_ms=v[0], fcrit_wait_ms=v[1], list_ms=v[2], gather_ms=v[3], tally_ms=v[4],
-                    launches=int(v[5]))
+                    launches=int(v[5]), gather_ms_phase=[v[6], v[7]], launches_phase=[int(v[8]), int(v[9])])
 
 
 class Graph:

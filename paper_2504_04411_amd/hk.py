@@ -103,6 +103,8 @@ def lib():
             "hk_f_quantile": ([c.c_double, c.c_double, c.c_double], c.c_double),
             "hk_profile_enable": ([_vp, c.c_int], c.c_int),
             "hk_profile_read": ([_vp, c.POINTER(c.c_double), c.c_int], c.c_int),
+            "hk_gather_phases": ([_vp, c.c_int, c.POINTER(c.c_int), c.POINTER(hk_photons), c.POINTER(c.c_int)],
+                                 c.c_int),
             "hk_mlp_param_count": ([], c.c_int),
             "hk_mlp_state_bytes": ([c.POINTER(c.c_size_t)], c.c_int),
             "hk_mlp_workspace_bytes": ([c.c_int64, c.POINTER(c.c_size_t)], c.c_int),
@@ -338,8 +340,17 @@ def hk_profile_enable(ctx, on: bool):
 
 
 def hk_profile_read(ctx):
-    out = (ctypes.c_double * 6)()
-    check(lib().hk_profile_read(ctx, out, 6))
+    out = (ctypes.c_double * 10)()
+    check(lib().hk_profile_read(ctx, out, 10))
+    return list(out)
+
+
+def hk_gather_phases(ctx, set_ids, photons):
+    n = len(set_ids)
+    ids = (ctypes.c_int * n)(*set_ids)
+    phs = (hk_photons * n)(*photons)
+    out = (ctypes.c_int * n)()
+    check(lib().hk_gather_phases(ctx, n, ids, phs, out))
     return list(out)
 
 

@@ -192,6 +192,10 @@ def test_two_gather_phases_graph_and_eager():
     eager.profile(False)
     print(f"  gather launches over 3 iterations: {prof['launches']}", flush=True)
     assert prof["launches"] == 6, "the batch was expected to be gathered in two phases"
+    assert prof["launches_phase"] == [3, 3]
+    phases = eager.gather_phases(ids, bufs)
+    assert sorted(set(phases)) == [0, 1], phases
+    print(f"  gather phase per set: {phases}", flush=True)
     for s in ids:
         trackers[s].finish(eager, s)
     g.close()
