@@ -345,10 +345,10 @@ int hk_profile_enable(hk_ctx *ctx, int on);
 int hk_profile_read(hk_ctx *ctx, double *out, int n);
 
 /* Which gather phase (0: first, 1: second) each of the n_sets sets would take in an hk_iterate call
- * with the same set_ids and light vertices (ph[s].n_stored is read, and whether ph[s].nrm[0] is NULL;
- * no pointer is dereferenced): phase[s] for set_ids[s]. Host-side, nothing is enqueued. Sets must have kernels
- * (HK_E_BAD_STATE); bad arguments give HK_E_INVALID_ARG. Used to attribute work to the two gather
- * launches of a batch when timing them. */
+ * with the same set_ids and light vertices: phase[s] for set_ids[s]. ph[s].n_stored is read, and
+ * whether ph[s].nrm[0] is NULL; no pointer is dereferenced. Host-side, nothing is enqueued. Sets
+ * must have kernels (HK_E_BAD_STATE); bad arguments give HK_E_INVALID_ARG. Used to attribute work
+ * to the two gather launches of a batch when timing them. */
 int hk_gather_phases(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, int *phase);
 
 int hk_version(void);
