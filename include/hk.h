@@ -347,7 +347,8 @@ int hk_profile_read(hk_ctx *ctx, double *out, int n);
 /* Which gather phase (0: first, 1: second) each of the n_sets sets would take in an hk_iterate call
  * with the same set_ids and light vertices: phase[s] for set_ids[s]. ph[s].n_stored is read, and
  * whether ph[s].nrm[0] is NULL; no pointer is dereferenced. Host-side, nothing is enqueued. Sets
- * must have kernels (HK_E_BAD_STATE); bad arguments give HK_E_INVALID_ARG. Used to attribute work
+ * must have kernels (HK_E_BAD_STATE); bad arguments (ids out of range or repeated, NULL arrays)
+ * give HK_E_INVALID_ARG. Used to attribute work
  * to the two gather launches of a batch when timing them. */
 int hk_gather_phases(hk_ctx *ctx, int n_sets, const int *set_ids, const hk_photons *ph, int *phase);
 

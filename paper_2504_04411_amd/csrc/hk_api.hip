@@ -1402,9 +1402,12 @@ extern "C" int hk_gather_phases(hk_ctx *ctx, int n_sets, const int *set_ids, con
     if (!ctx || !phase) return fail(HK_E_INVALID_ARG, "bad arguments");
     if (n_sets < 1 || n_sets > MAX_SETS || !set_ids || !ph)
         return fail(HK_E_INVALID_ARG, "bad set arguments (n_sets in [1, %d], arrays non-NULL)", MAX_SETS);
+    bool seen[MAX_SETS] = {};
     for (int s = 0; s < n_sets; ++s) {
         const int id = set_ids[s];
         if (id < 0 || id >= MAX_SETS) return fail(HK_E_INVALID_ARG, "set id %d out of range", id);
+        if (seen[id]) return fail(HK_E_INVALID_ARG, "set id %d appears twice in one call", id);
+        seen[id] = true;
         if (!ctx->sets[id].init) return fail(HK_E_BAD_STATE, "set %d has no kernels (call hk_set_kernels)", id);
         if (ph[s].n_stored < 0) return fail(HK_E_INVALID_ARG, "set %d: n_stored < 0", id);
     }

@@ -105,6 +105,24 @@ def test_duplicate_set_ids_are_refused():
     est.close()
 
 
+def test_gather_phases_query():
+    """hk_gather_phases (host-side): one set takes one phase; a set without kernels is refused with
+    HK_E_BAD_STATE, an id out of range, a repeated id and a NULL output with HK_E_INVALID_ARG."""
+    hk, DevicePhotons, Estimator, G = _mods()
+    w = G.small_config0(seed=1, n_side=4, J=100)
+    est = Estimator(w.params.r1)
+    est.set_kernels(0, w.kernels.pos)
+    ph = DevicePhotons.upload(w.photons(0))
+    assert est.gather_phases([0], [ph]) == [0]
+    assert _code(est.gather_phases, [1], [ph]) == hk.HK_E_BAD_STATE
+    assert _code(est.gather_phases, [300], [ph]) == hk.HK_E_INVALID_ARG
+    assert _code(est.gather_phases, [0, 0], [ph, ph]) == hk.HK_E_INVALID_ARG
+    ids = (ctypes.c_int * 1)(0)
+    phs = (hk.hk_photons * 1)(ph.struct())
+    assert hk.lib().hk_gather_phases(est.ctx, 1, ids, phs, None) == hk.HK_E_INVALID_ARG
+    est.close()
+
+
 def test_max_iters_reached_is_bad_state():
     hk, DevicePhotons, Estimator, G = _mods()
     w = G.small_config0(seed=1, n_side=4, J=500)
