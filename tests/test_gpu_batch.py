@@ -201,6 +201,35 @@ def test_two_gather_phases_graph_and_eager():
     g.close()
 
 
+def test_two_phases_on_a_side_stream_match_the_default_stream():
+    """The eight-set batch of the test above (two gather phases, the second phase's grids built beside
+    the first gather) called on a stream of the caller's own, with unrelated work queued on the
+    default stream meanwhile, leaves every set bit-identical to the same calls on the default stream:
+    the library's forks and joins follow whichever stream it is given."""
+    G, GP, DP = _mods()
+    ws = G.config2(seed=2, n_sets=8, n_iter=3, scale=0.3)
+    on_default = GP.make_estimator(ws[0])
+    on_side = GP.make_estimator(ws[0])
+    for s, w in enumerate(ws):
+        _add_set(on_default, s, w)
+        _add_set(on_side, s, w)
+    ids = list(range(len(ws)))
+    side = torch.cuda.Stream()
+    for it in range(2):
+        phs = [DP.upload(w.photons(it)) for w in ws]
+        torch.cuda.synchronize()
+        on_default.iterate(ids, phs)
+        with torch.cuda.stream(side):
+            on_side.iterate(ids, phs)
+        x = torch.randn(1 << 22, device="cuda")
+        (x * 2.0).sum()
+        torch.cuda.synchronize()
+    for s in ids:
+        _same(_snapshot(on_side, s), _snapshot(on_default, s), f"side stream, set {s}")
+    on_default.close()
+    on_side.close()
+
+
 def test_graph_refuses_stale_sets():
     """A graph whose set was re-initialised, or that reached max_iters, is refused on the host."""
     G, GP, DP = _mods()
