@@ -148,8 +148,11 @@ int hk_set_kernels(hk_ctx *ctx, int set_id, int64_t n, double r1, double rmin, c
  * set s's light vertices, state[s] its state, set_ids[s] its id. Each set's grid is built by its own
  * launches; the gather, test and update of up to 64 sets (at most 2^27 - 65 stored light vertices in
  * total, 89,478,421 with the normal test or vertex merging, whose payload records are 48 bytes)
- * run as ONE launch over a work list spanning those sets, so many small, uneven sets fill the GPU
- * together. Sets with and without the normal test go to separate launches. `workspace` (device,
+ * run as one launch over a work list spanning those sets, so many small, uneven sets fill the GPU
+ * together; a batch of several sets may be gathered in two such launches (phases), the second
+ * phase's grids being built while the first phase gathers (hk_gather_phases tells which sets go
+ * where). Sets with and without the normal test go to separate launches. The grids are built on
+ * streams of the library's own, forked from and joined back to `stream` with events. `workspace` (device,
  * workspace_bytes long) must hold hk_workspace_bytes_batch over the sets (HK_E_SMALL_BUFFER
  * otherwise); a set holds at most 2^27 - 65 stored light vertices per iteration, 89,478,421 with the
  * normal test or vertex merging (HK_E_UNSUPPORTED).
